@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Nothing here touches the GPU.  Each test checks the oracle against an
+independent fact: a value the paper prints, a closed form, a library
+routine, or brute force written separately in numpy.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import ctf_synth as cs
+import oracle as O
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_pins.json")))
+
+
+# ---------------------------------------------------------------------------
+# Figure 3: the bijection h and its inverse
+# ---------------------------------------------------------------------------
+
+def _mask_from_bits(bits):
+    B = np.zeros(4, np.uint64)
+    for b in bits:
+        B[b >> 6] |= np.uint64(1) << np.uint64(b & 63)
+    return B
+
+
+def test_figure3_worked_example():
+    g = GOLD["figure3_bijection"]
+    B = _mask_from_bits(g["set_bits"])
+    for i, t in g["h"]:
+        assert O.bit_select(B, i) == t
+    for t, i in g["h_inv"]:
+        assert O.bit_rank(B, t) == i
+
+
+def test_bijection_against_numpy_random_masks():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        bits = np.flatnonzero(rng.random(256) < rng.uniform(0.02, 0.6))
+        B = _mask_from_bits(bits)
+        for i, t in enumerate(bits):
+            assert O.bit_select(B, i) == t
+            assert O.bit_rank(B, int(t)) == i          # round trip
+        assert O.bit_select(B, len(bits)) == -1
+        for t in rng.integers(0, 256, 20):
+            assert O.bit_rank(B, int(t)) == int((bits < t).sum())
+
+
+# ---------------------------------------------------------------------------
+# procedural texture
+# ---------------------------------------------------------------------------
+
+def test_sinusoid_texture_matches_fft_spectrum():
+    """The 2-D DFT of one channel has exactly the drawn (p, q, j, a) lines.
+
+    sin(2 pi (p x + q y + j)/W) contributes (W^2 / 2i) e^{2 pi i j / W} at
+    frequency (kx, ky) = (p, q) mod W and the conjugate at (-p, -q).
+    """
+    W, K = 64, 8
+    pqj, amp = cs.sinusoid_params(W, K, 8, seed=5)
+    tex = O.sinusoid_texture(W, pqj, amp)
+    ys, xs = np.mgrid[0:W, 0:W]
+    vals = tex.eval(np.stack([xs.ravel(), ys.ravel()], -1)).reshape(W, W, 4)
+    for c in range(4):
+        F = np.fft.fft2(vals[..., c])          # F[ky, kx] = sum f e^{-2pi i (kx x + ky y)/W}
+        expect = np.zeros((W, W), complex)
+        expect[0, 0] += 0.5 * W * W
+        for (p, q, j), a in zip(pqj[c], amp[c]):
+            coef = 0.5 * float(a) * W * W / 2j
+            expect[q % W, p % W] += coef * np.exp(2j * np.pi * j / W)
+            expect[(-q) % W, (-p) % W] += np.conj(coef * np.exp(2j * np.pi * j / W))
+        np.testing.assert_allclose(F, expect, atol=1e-8 * W * W)
+
+
+def test_sinusoid_texture_periodic_and_in_range():
+    W = 2048
+    pqj, amp = cs.sinusoid_params(W, 32, 64, seed=2)
+    tex = O.sinusoid_texture(W, pqj, amp)
+    rng = np.random.default_rng(0)
+    xy = rng.integers(-5000, 5000, (2000, 2)).astype(np.int32)
+    a = tex.eval(xy)
+    for shift in ((W, 0), (0, W), (-W, 3 * W)):
+        b = tex.eval(xy + np.array(shift, np.int32))
+        assert np.array_equal(a, b)
+    assert a.min() >= 0.0 and a.max() <= 1.0
+
+
+# ---------------------------------------------------------------------------
+# footprint and weights: closed forms
+# ---------------------------------------------------------------------------
+
+ALL = [O.BILINEAR4, O.LIST, O.BOX, O.MASK]
+
+
+@pytest.fixture(scope="module")
+def c0_scene():
+    return cs.tilted_plane_scene()
+
+
+@pytest.mark.parametrize("kind", ALL)
+def test_affine_texture_reproduced_exactly(c0_scene, kind):
+    """Bilinear filtering reproduces an affine function of the texel lattice.
+
+    With f = a + b x + c y, the filtered value at the lane's filter position
+    (x0 + s, y0 + t) is a + b (x0 + s) + c (y0 + t), for every exactly
+    filtered lane.
+    """
+    sc = c0_scene
+    coef = cs.affine_params(1)
+    tex = O.affine_texture(64, 64, coef)
+    r = O.filter(sc.uv, sc.duv, tex, O.method(kind, box=(4, 4)), seed=0, stf=True)
+    # float32 texel position (one rounding, as the method's fma), then the
+    # filter position x0 + s with s = fx - x0 taken in float32 as the paper's
+    # code does (inexact for -1 < fx < 0)
+    def pos(c):
+        f = (sc.uv[..., c].astype(np.float64) * 64 - 0.5).astype(np.float32)
+        f0 = np.floor(f)
+        return f0.astype(np.float64) + (f - f0).astype(np.float64)
+    fx, fy = pos(0), pos(1)
+    exact = r["stf"][..., 0] == np.iinfo(np.int32).min
+    assert exact.sum() > 1000
+    for ch in range(4):
+        want = coef[ch, 0] + coef[ch, 1] * fx + coef[ch, 2] * fy
+        np.testing.assert_allclose(r["out"][..., ch][exact], want[exact], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ALL + [O.STF1])
+def test_constant_texture(c0_scene, kind):
+    sc = c0_scene
+    rgba = (0.25, 0.5, 0.75, 1.0)
+    tex = O.constant_texture(64, 64, rgba)
+    r = O.filter(sc.uv, sc.duv, tex, O.method(kind, box=(4, 4)), seed=7)
+    act = np.isfinite(sc.uv).all(-1)
+    assert np.all(r["out"][act] == np.array(rgba))
+
+
+def test_texel_centres_return_texel_values():
+    """uv at texel centres gives s = t = 0: the output is f(x, y) itself."""
+    W = 64
+    pqj, amp = cs.sinusoid_params(W, 8, 8, seed=0)
+    tex = O.sinusoid_texture(W, pqj, amp)
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, W, (16, 16))
+    ys = rng.integers(0, W, (16, 16))
+    uv = np.stack([(xs + 0.5) / W, (ys + 0.5) / W], -1).astype(np.float32)
+    duv = np.zeros((16, 16, 4), np.float32)
+    want = tex.eval(np.stack([xs.ravel(), ys.ravel()], -1)).reshape(16, 16, 4)
+    for kind in ALL + [O.STF1]:
+        r = O.filter(uv, duv, tex, O.method(kind), seed=3)
+        np.testing.assert_array_equal(r["out"], want)
+
+
+# ---------------------------------------------------------------------------
+# unique sets, masks, boxes
+# ---------------------------------------------------------------------------
+
+def _numpy_footprints(uv, W):
+    """Independent float32 footprint: floor(u*W - 0.5) with one rounding."""
+    f = (uv.astype(np.float64) * W - 0.5).astype(np.float32)
+    return np.floor(f).astype(np.int64)
+
+
+def test_lists_and_masks_against_numpy(c0_scene):
+    sc = c0_scene
+    W = 64
+    pqj, amp = cs.sinusoid_params(W, 8, 8, seed=0)
+    tex = O.sinusoid_texture(W, pqj, amp)
+    rl = O.filter(sc.uv, sc.duv, tex, O.method(O.LIST), lists=True)
+    rm = O.filter(sc.uv, sc.duv, tex, O.method(O.MASK), lists=True)
+    rb = O.filter(sc.uv, sc.duv, tex, O.method(O.BOX), lists=True)
+    x0y0 = _numpy_footprints(sc.uv, W)
+    tiles_x = sc.width // 8
+    checked = 0
+    for t in range(len(rl["stats"])):
+        S = rl["stats"][t]
+        ty, tx = divmod(t, tiles_x)
+        lanes = [l for l in range(64) if (int(S["part"]) >> l) & 1]
+        pts = set()
+        for l in lanes:
+            x0, y0 = x0y0[ty * 8 + l // 8, tx * 8 + l % 8]
+            pts |= {(x0 + dx, y0 + dy) for dx in (0, 1) for dy in (0, 1)}
+        U = sorted(pts, key=lambda p: (p[1], p[0]))
+        assert S["unique"] == len(U)
+        if not lanes:
+            continue
+        xs = [p[0] for p in U]
+        ys = [p[1] for p in U]
+        assert (S["xmin"], S["ymin"]) == (min(xs), min(ys))
+        assert (S["bbw"], S["bbh"]) == (max(xs) - min(xs) + 1, max(ys) - min(ys) + 1)
+        if S["flags"] & O.TILE_OK:
+            got = [tuple(e) for e in rl["lists"][t, :S["n"]]]
+            assert got == U
+            checked += 1
+        Sm = rm["stats"][t]
+        if S["bbw"] <= 16 and S["bbh"] <= 16:
+            # invariant: popcount of the 16x16 mask is the exact unique count
+            pc = sum(bin(int(w)).count("1") for w in Sm["mask"])
+            assert pc == len(U) == Sm["n"]
+            # Mask and List succeed on the same waves
+            assert bool(Sm["flags"] & O.TILE_OK) == bool(S["flags"] & O.TILE_OK)
+            if Sm["flags"] & O.TILE_OK:
+                assert [tuple(e) for e in rm["lists"][t, :Sm["n"]]] == U
+        Sb = rb["stats"][t]
+        assert Sb["n"] == S["bbw"] * S["bbh"]
+        if Sb["flags"] & O.TILE_OK:
+            cells = [(S["xmin"] + i % S["bbw"], S["ymin"] + i // S["bbw"]) for i in range(Sb["n"])]
+            assert [tuple(e) for e in rb["lists"][t, :Sb["n"]]] == cells
+    assert checked > 500
+
+
+def _quad_tiles(tile, mags, angles, offsets):
+    """One head-on rotated-quad tile per (mag, angle, offset), side by side."""
+    tw, th = tile
+    n = len(mags)
+    uv = np.zeros((th, tw * n, 2), np.float32)
+    duv = np.zeros((th, tw * n, 4), np.float32)
+    for i in range(n):
+        u, d = cs.head_on_quad_uv(tw, th, mags[i], angles[i], offsets[i])
+        uv[:, i * tw:(i + 1) * tw] = u
+        duv[:, i * tw:(i + 1) * tw] = d
+    return uv, duv
+
+
+def _quad_stats(tile, mags, angles, offsets, meth):
+    uv, duv = _quad_tiles(tile, mags, angles, offsets)
+    tex = O.constant_texture(4096, 4096, (0, 0, 0, 0))
+    return O.filter(uv, duv, tex, meth, tile=tile)["stats"]
+
+
+@pytest.mark.slow
+def test_paper_max_unique_54_at_mag1():
+    g = GOLD["max_unique_8x4_mag1"]
+    rng = np.random.default_rng(11)
+    angs = np.concatenate([np.radians(np.arange(0, 90.01, 0.5)),
+                           np.radians(rng.uniform(28, 32, 4000)),
+                           np.radians(rng.uniform(58, 62, 4000))])
+    angs = np.repeat(angs, 40)
+    offs = rng.uniform(0, 64, (len(angs), 2)) + 1000
+    st = _quad_stats(tuple(g["tile"]), np.full(len(angs), g["magnification"]), angs, offs,
+                     O.method(O.LIST))
+    u = st["unique"]
+    assert u.max() == g["max_unique"]
+    best = np.degrees(angs[u == u.max()]) % 90
+    assert np.all((np.abs(best - 30) < 5) | (np.abs(best - 60) < 5))
+
+
+@pytest.mark.slow
+def test_paper_exact_set_threshold_159():
+    g = GOLD["exact_set_threshold_8x4"]
+    rng = np.random.default_rng(12)
+    angs = np.repeat(np.radians(np.arange(0, 90.01, 0.25)), 60)
+    offs = rng.uniform(0, 64, (len(angs), 2)) + 1000
+    for meth in (O.method(O.LIST), O.method(O.MASK)):
+        above = _quad_stats(tuple(g["tile"]), np.full(len(angs), 1.595), angs, offs, meth)
+        assert np.all(above["flags"] & O.TILE_OK)
+        below = _quad_stats(tuple(g["tile"]), np.full(len(angs), 1.575), angs, offs, meth)
+        assert np.any((below["flags"] & O.TILE_OK) == 0)
+
+
+@pytest.mark.slow
+def test_paper_box_threshold_235_at_45deg():
+    """Box succeeds for every offset iff the rotated tile's span stays below 3 texels.
+
+    At 45 degrees an 8x4 tile spans (7 + 3)/(sqrt 2 m) texels per axis, so
+    success is guaranteed from m = 10 / (3 sqrt 2) = 2.357 (the paper's 2.35).
+    """
+    g = GOLD["box_threshold_8x4_45deg"]
+    rng = np.random.default_rng(13)
+    n = 20000
+    angs = np.full(n, math.radians(g["angle_deg"]))
+    offs = rng.uniform(0, 64, (n, 2)) + 1000
+    m_star = 10 / (3 * math.sqrt(2))
+    assert abs(m_star - g["magnification"]) < 0.01
+    ok = _quad_stats(tuple(g["tile"]), np.full(n, m_star * 1.001), angs, offs, O.method(O.BOX))
+    assert np.all(ok["flags"] & O.TILE_OK)
+    bad = _quad_stats(tuple(g["tile"]), np.full(n, 2.30), angs, offs, O.method(O.BOX))
+    assert np.any((bad["flags"] & O.TILE_OK) == 0)
+
+
+# ---------------------------------------------------------------------------
+# stochastic draw
+# ---------------------------------------------------------------------------
+
+def _pcg_inverse(y):
+    """Independent inverse of the published pcg hash (each step is a bijection)."""
+    M32 = 0xFFFFFFFF
+    x = y ^ (y >> 22)                       # undo word ^ (word >> 22)
+    w = (x * pow(277803737, -1, 2**32)) & M32
+    sh = (w >> 28) + 4                      # top 4 bits survive the xorshift
+    s = w
+    for _ in range(8):
+        s = w ^ (s >> sh)
+    return ((s - 2891336453) * pow(747796405, -1, 2**32)) & M32
+
+
+def test_pcg_hash_is_the_published_permutation():
+    rng = np.random.default_rng(4)
+    for v in list(rng.integers(0, 2**32, 3000)) + [0, 1, 2**31, 2**32 - 1]:
+        v = int(v)
+        assert _pcg_inverse(O.pcg_hash(v)) == v
+    # avalanche: flipping one input bit flips about half the output bits
+    flips = []
+    for v in rng.integers(0, 2**32, 300):
+        h = O.pcg_hash(int(v))
+        for b in range(32):
+            flips.append(bin(h ^ O.pcg_hash(int(v) ^ (1 << b))).count("1"))
+    assert 14.5 < np.mean(flips) < 17.5
+
+
+def test_stf_draw_frequencies_match_weights():
+    """P(texel k) = bilinear weight k (chi-square over many pixels)."""
+    from scipy.stats import chisquare
+    W = 64
+    s, t = 0.3, 0.8
+    n = 256
+    uv = np.empty((n, n, 2), np.float32)
+    uv[..., 0] = (10 + s + 0.5) / W
+    uv[..., 1] = (20 + t + 0.5) / W
+    duv = np.full((n, n, 4), 1.0, np.float32)     # minifying: every lane draws
+    tex = O.constant_texture(W, W, (0, 0, 0, 0))
+    r = O.filter(uv, duv, tex, O.method(O.LIST), seed=12345, stf=True)
+    pick = r["stf"].reshape(-1, 2)
+    assert pick[:, 0].min() >= 10 and pick[:, 0].max() <= 11
+    k = (pick[:, 0] - 10) + 2 * (pick[:, 1] - 20)
+    counts = np.bincount(k, minlength=4)
+    ss = float(np.float32(uv[0, 0, 0] * np.float32(W) - np.float32(0.5))) - 10
+    tt = float(np.float32(uv[0, 0, 1] * np.float32(W) - np.float32(0.5))) - 20
+    w = np.array([(1 - ss) * (1 - tt), ss * (1 - tt), (1 - ss) * tt, ss * tt])
+    w /= w.sum()
+    assert chisquare(counts, w * counts.sum()).pvalue > 1e-3
+    # s = t = 0: the draw is always the upper-left texel
+    uv[..., 0] = (10 + 0.5) / W
+    uv[..., 1] = (20 + 0.5) / W
+    r = O.filter(uv, duv, tex, O.method(O.LIST), seed=9, stf=True)
+    assert np.all(r["stf"].reshape(-1, 2) == np.array([10, 20]))
+
+
+def test_minify_lanes_draw_and_magnify_lanes_do_not(c0_scene):
+    sc = c0_scene
+    tex = O.constant_texture(64, 64, (1, 1, 1, 1))
+    r = O.filter(sc.uv, sc.duv, tex, O.method(O.LIST), stf=True)
+    ratio = cs.texel_ratio(sc.duv, 64, 64)
+    drew = r["stf"][..., 0] != np.iinfo(np.int32).min
+    ok = np.zeros(sc.uv.shape[:2], bool)
+    tiles_x = sc.width // 8
+    for t, S in enumerate(r["stats"]):
+        if S["flags"] & O.TILE_OK:
+            ty, tx = divmod(t, tiles_x)
+            ok[ty * 8:(ty + 1) * 8, tx * 8:(tx + 1) * 8] = True
+    # in successful tiles, a lane draws iff its footprint spans more than a texel
+    # (away from ties at exactly one texel, which float32 rounding decides)
+    clear = ok & (np.abs(ratio - 1) > 1e-5)
+    assert np.array_equal(drew[clear], ratio[clear] > 1)
+
+
+# ---------------------------------------------------------------------------
+# decoder (float64)
+# ---------------------------------------------------------------------------
+
+def test_decoder_identity_network_is_bilinear_latents():
+    """A network that passes features through reduces to latent interpolation.
+
+    With H = 16, W1 = W2 = identity on the 16 features, W3 summing feature c
+    (level 0) and feature 8 + c (level 1) into output c, zero biases and
+    positive latents, the output equals the sum of the two levels' bilinear
+    samples with repeat addressing -- scipy's map_coordinates (order 1,
+    mode 'grid-wrap') computes those independently.
+    """
+    from scipy.ndimage import map_coordinates
+    tex_w, l0, l1, H, C = 32, 8, 4, 16, 8
+    lay = cs.decoder_layout(l0, l1, H, C)
+    rng = np.random.default_rng(2)
+    p = np.zeros(lay["total"][1])
+    o, n = lay["lat0"]; p[o:o + n] = rng.uniform(0.1, 1, n)
+    o, n = lay["lat1"]; p[o:o + n] = rng.uniform(0.1, 1, n)
+    o, n = lay["W1"]; p[o:o + n] = np.eye(16).ravel()
+    o, n = lay["W2"]; p[o:o + n] = np.eye(16).ravel()
+    W3 = np.zeros((16, 4))
+    for c in range(4):
+        W3[c, c] = 1
+        W3[8 + c, c] = 1
+    o, n = lay["W3"]; p[o:o + n] = W3.ravel()
+    tex = O.decoder_texture(tex_w, l0, l1, H, p)
+    xy = rng.integers(-40, 80, (300, 2)).astype(np.int32)
+    got = tex.eval(xy)
+    want = np.zeros_like(got)
+    for name, L in (("lat0", l0), ("lat1", l1)):
+        o, n = lay[name]
+        grid = p[o:o + n].reshape(L, L, C)
+        gx = (xy[:, 0] + 0.5) * L / tex_w - 0.5
+        gy = (xy[:, 1] + 0.5) * L / tex_w - 0.5
+        for c in range(4):
+            want[:, c] += map_coordinates(grid[..., c], [gy, gx], order=1, mode="grid-wrap")
+    np.testing.assert_allclose(got, want, atol=1e-12)
+
+
+def test_decoder_gradient_finite_differences_4x4_width4():
+    """Analytic float64 gradient vs central differences (4x4 latent grid, 4-wide MLP)."""
+    tex_w, l0, l1, H = 16, 4, 2, 4
+    p = cs.decoder_init(l0, l1, H, seed=1, latent_range=0.5).astype(np.float64)
+    rng = np.random.default_rng(5)
+    xy = rng.integers(0, tex_w, (64, 2)).astype(np.int32)
+    target = rng.uniform(0, 1, (64, 4)).astype(np.float32)
+    loss, g = O.decoder_loss_grad(p, xy, target, l0, l1, H, tex_w)
+    eps = 1e-6
+    fd = np.empty_like(p)
+    for i in range(p.size):
+        q = p.copy(); q[i] += eps
+        lp, _ = O.decoder_loss_grad(q, xy, target, l0, l1, H, tex_w, grad=False)
+        q[i] -= 2 * eps
+        lm, _ = O.decoder_loss_grad(q, xy, target, l0, l1, H, tex_w, grad=False)
+        fd[i] = (lp - lm) / (2 * eps)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-8)
+    assert np.abs(g).max() > 1e-3
