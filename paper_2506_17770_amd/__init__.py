@@ -1,0 +1,307 @@
+"""Collaborative texture filtering on MI355X (gfx950): Python binding.
+
+A thin ctypes layer over ``libctf.so`` (the C ABI declared in
+``include/ctf.h``).  It only marshals arguments: every step of the filter
+runs in the library's HIP kernels.  Device buffers are torch tensors on a
+ROCm device; streams are torch streams.  If the library has not been built
+this module raises on import (no CPU fallback exists).
+
+Paper: Akenine-Moller, Ebelin, Pharr, Wronski, "Collaborative Texture
+Filtering", HPG 2025 (arXiv 2506.17770).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctf.so")
+
+BILINEAR4, STF1, LIST, BOX, MASK = 0, 1, 2, 3, 4
+FB_STF1, FB_C, FB_CPLUS = 0, 1, 2
+TEX_SINUSOIDS, TEX_AFFINE, TEX_CONSTANT, TEX_TABLE, TEX_DECODER = 0, 1, 2, 3, 4
+FP16, BF16 = 0, 1
+TILE_OK, TILE_CAP, TILE_OVERFLOW, TILE_EMPTY = 1, 2, 4, 8
+MAX_ITEMS = 256
+METHOD_NAMES = {BILINEAR4: "bilinear4", STF1: "stf1", LIST: "list", BOX: "box", MASK: "mask"}
+
+TILE_STATS_DTYPE = np.dtype([
+    ("active", "<u8"), ("part", "<u8"), ("stf", "<u8"), ("mask", "<u8", (4,)),
+    ("xmin", "<i4"), ("ymin", "<i4"), ("bbw", "<i4"), ("bbh", "<i4"),
+    ("n", "<i4"), ("unique", "<i4"), ("evals", "<i4"), ("flags", "<i4"),
+    ("reserved", "<i4", (10,))])
+FRAME_STATS_FIELDS = ("evals", "active", "stf", "minify", "tiles", "tiles_ok", "tiles_fail", "rows")
+
+
+class CtfError(RuntimeError):
+    pass
+
+
+class TextureDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("n_terms", ctypes.c_int32), ("pqj", ctypes.c_void_p), ("amp", ctypes.c_void_p),
+                ("affine", (ctypes.c_float * 3) * 4), ("constant", ctypes.c_float * 4),
+                ("table", ctypes.c_void_p), ("decoder", ctypes.c_void_p),
+                ("precision", ctypes.c_int32), ("reserved_", ctypes.c_int32 * 3)]
+
+
+class Method(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("box_w", ctypes.c_int32), ("box_h", ctypes.c_int32),
+                ("mask_side", ctypes.c_int32), ("max_evals_per_lane", ctypes.c_int32),
+                ("fallback", ctypes.c_int32)]
+
+
+class DecoderDesc(ctypes.Structure):
+    _fields_ = [("l0", ctypes.c_int32), ("l1", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("tex_w", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32 * 3)]
+
+
+# every entry point of include/ctf.h: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I32, _I64, _U64, _SZ, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_float
+SIGNATURES = {
+    "ctf_last_error": (ctypes.c_char_p, []),
+    "ctf_create": (_I32, [ctypes.c_int, _P]),
+    "ctf_destroy": (_I32, [_P]),
+    "ctf_texture_create": (_I32, [_P, _P, _P]),
+    "ctf_texture_destroy": (_I32, [_P]),
+    "ctf_texture_eval": (_I32, [_P, _P, _I64, _P, _P]),
+    "ctf_filter": (_I32, [_P, _P, _P, _I32, _I32, _P, _P, _U64, _P, _P, _P, _P, _P, _P]),
+    "ctf_decoder_param_count": (_SZ, [_P]),
+    "ctf_decoder_create": (_I32, [_P, _P, _P, _P]),
+    "ctf_decoder_destroy": (_I32, [_P]),
+    "ctf_decoder_get_params": (_I32, [_P, _P, _SZ]),
+    "ctf_decoder_set_params": (_I32, [_P, _P, _SZ]),
+    "ctf_decoder_state_bytes": (_SZ, [_P]),
+    "ctf_decoder_get_state": (_I32, [_P, _P, _SZ]),
+    "ctf_decoder_set_state": (_I32, [_P, _P, _SZ]),
+    "ctf_decoder_loss_grad": (_I32, [_P, _P, _P, _I32, _I32, _P, _P, _P]),
+    "ctf_decoder_train": (_I32, [_P, _P, _I64, _I32, _F, _U64, _I32, _P, _P]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2506_17770_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != 0:
+        raise CtfError(f"ctf error {rc}: {lib.ctf_last_error().decode()}")
+
+
+def _dptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise CtfError("expected a tensor in GPU memory")
+    if not t.is_contiguous():
+        raise CtfError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1) -> Method:
+    return Method(kind, box[0], box[1], mask_side, k, fallback)
+
+
+class Context:
+    """A library context on one GPU (owns its textures and decoders)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib.ctf_create(device, ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _check(lib.ctf_destroy(self.handle))
+            self.handle = None
+
+    # -- textures -----------------------------------------------------------
+    def _texture(self, desc: TextureDesc, keep=()):
+        h = ctypes.c_void_p()
+        _check(lib.ctf_texture_create(self.handle, ctypes.byref(desc), ctypes.byref(h)))
+        return Texture(self, h, desc.kind, desc.width, desc.height)
+
+    def sinusoid_texture(self, width, pqj, amp):
+        pqj = np.ascontiguousarray(pqj, dtype=np.int32)
+        amp = np.ascontiguousarray(amp, dtype=np.float32)
+        d = TextureDesc()
+        d.kind, d.width, d.height, d.n_terms = TEX_SINUSOIDS, width, width, pqj.shape[1]
+        d.pqj, d.amp = pqj.ctypes.data, amp.ctypes.data
+        return self._texture(d, (pqj, amp))
+
+    def affine_texture(self, width, height, coef):
+        d = TextureDesc()
+        d.kind, d.width, d.height = TEX_AFFINE, width, height
+        coef = np.asarray(coef, dtype=np.float64).reshape(4, 3)
+        for c in range(4):
+            for j in range(3):
+                d.affine[c][j] = float(coef[c, j])
+        return self._texture(d)
+
+    def constant_texture(self, width, height, rgba):
+        d = TextureDesc()
+        d.kind, d.width, d.height = TEX_CONSTANT, width, height
+        for c in range(4):
+            d.constant[c] = float(rgba[c])
+        return self._texture(d)
+
+    def table_texture(self, table):
+        table = np.ascontiguousarray(table, dtype=np.float32)
+        h, w, _ = table.shape
+        d = TextureDesc()
+        d.kind, d.width, d.height = TEX_TABLE, w, h
+        d.table = table.ctypes.data
+        return self._texture(d, (table,))
+
+    def decoder_texture(self, decoder: "Decoder", precision=FP16):
+        d = TextureDesc()
+        d.kind, d.width, d.height = TEX_DECODER, decoder.tex_w, decoder.tex_w
+        d.decoder, d.precision = decoder.handle.value, precision
+        return self._texture(d)
+
+    # -- filtering ----------------------------------------------------------
+    def filter(self, uv, duv, tex: "Texture", meth: Method, seed=0, out=None, tile_stats=None,
+               frame_stats=None, lists=None, stf=None, stream=None):
+        """ctf_filter on torch tensors; optional outputs are tensors or None."""
+        sh, sw = uv.shape[:2]
+        if uv.shape[-1] != 2 or tuple(duv.shape) != (sh, sw, 4):
+            raise CtfError("uv must be [H][W][2] and duv [H][W][4]")
+        if out is None:
+            import torch
+            out = torch.empty((sh, sw, 4), dtype=torch.float32, device=uv.device)
+        _check(lib.ctf_filter(self.handle, _dptr(uv), _dptr(duv), sw, sh, tex.handle,
+                              ctypes.byref(meth), seed & (2**64 - 1), _dptr(out),
+                              _dptr(tile_stats), _dptr(frame_stats), _dptr(lists), _dptr(stf),
+                              _stream(stream)))
+        return out
+
+    def decoder(self, l0, l1, hidden, tex_w, init, channels=8) -> "Decoder":
+        return Decoder(self, l0, l1, hidden, tex_w, init, channels)
+
+
+class Texture:
+    def __init__(self, ctx: Context, handle, kind, width, height):
+        self.ctx, self.handle, self.kind, self.width, self.height = ctx, handle, kind, width, height
+
+    def eval(self, xy, out=None, stream=None):
+        """Texel values rgba[i] = f(xy[i]); xy int32 [n][2] on the GPU."""
+        import torch
+        n = xy.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=xy.device)
+        _check(lib.ctf_texture_eval(self.handle, _dptr(xy), n, _dptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if self.handle:
+            _check(lib.ctf_texture_destroy(self.handle))
+            self.handle = None
+
+
+class Decoder:
+    """Latent-grid + MLP texel decoder with float32 master parameters."""
+
+    def __init__(self, ctx: Context, l0, l1, hidden, tex_w, init, channels=8):
+        self.ctx = ctx
+        self.desc = DecoderDesc(l0, l1, hidden, channels, tex_w)
+        self.tex_w = tex_w
+        self.count = lib.ctf_decoder_param_count(ctypes.byref(self.desc))
+        init = np.ascontiguousarray(init, dtype=np.float32)
+        if init.size != self.count:
+            raise CtfError(f"init has {init.size} values, decoder needs {self.count}")
+        h = ctypes.c_void_p()
+        _check(lib.ctf_decoder_create(ctx.handle, ctypes.byref(self.desc), init.ctypes.data,
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.count, np.float32)
+        _check(lib.ctf_decoder_get_params(self.handle, out.ctypes.data, self.count))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib.ctf_decoder_set_params(self.handle, p.ctypes.data, p.size))
+
+    def state(self) -> bytes:
+        n = lib.ctf_decoder_state_bytes(self.handle)
+        buf = ctypes.create_string_buffer(n)
+        _check(lib.ctf_decoder_get_state(self.handle, buf, n))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        _check(lib.ctf_decoder_set_state(self.handle, blob, len(blob)))
+
+    def loss_grad(self, xy, target, precision=BF16, stream=None):
+        import torch
+        loss = torch.zeros(1, dtype=torch.float32, device=xy.device)
+        grad = torch.zeros(self.count, dtype=torch.float32, device=xy.device)
+        _check(lib.ctf_decoder_loss_grad(self.handle, _dptr(xy), _dptr(target), xy.shape[0],
+                                         precision, _dptr(loss), _dptr(grad), _stream(stream)))
+        return loss, grad
+
+    def train(self, target: Texture, steps, batch=65536, lr=1e-3, seed=0, precision=BF16,
+              loss_trace=None, stream=None):
+        _check(lib.ctf_decoder_train(self.handle, target.handle, steps, batch, lr,
+                                     seed & (2**64 - 1), precision, _dptr(loss_trace),
+                                     _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _check(lib.ctf_decoder_destroy(self.handle))
+            self.handle = None
+
+
+def tile_stats_buffer(sw, sh, device="cuda"):
+    import torch
+    tiles = ((sw + 7) // 8) * ((sh + 7) // 8)
+    return torch.zeros((tiles, TILE_STATS_DTYPE.itemsize), dtype=torch.uint8, device=device)
+
+
+def frame_stats_buffer(device="cuda"):
+    import torch
+    return torch.zeros(16, dtype=torch.int64, device=device)
+
+
+def tile_stats_numpy(buf) -> np.ndarray:
+    return buf.cpu().numpy().view(TILE_STATS_DTYPE).reshape(-1)
+
+
+def frame_stats_dict(buf) -> dict:
+    v = buf.cpu().numpy().astype(np.int64)
+    return {k: int(v[i]) for i, k in enumerate(FRAME_STATS_FIELDS)}
+
+
+def lists_buffer(sw, sh, device="cuda"):
+    import torch
+    tiles = ((sw + 7) // 8) * ((sh + 7) // 8)
+    return torch.full((tiles, MAX_ITEMS, 2), -2**31, dtype=torch.int32, device=device)
+
+
+def stf_buffer(sw, sh, device="cuda"):
+    import torch
+    return torch.full((sh, sw, 2), -2**31, dtype=torch.int32, device=device)

@@ -1,0 +1,276 @@
+// api.hip -- the C ABI (include/ctf.h): contexts, textures, filtering.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctf.h"
+#include "ctf_internal.h"
+
+namespace ctf {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+}  // namespace ctf
+
+using namespace ctf;
+
+namespace {
+
+ctf_status fail(ctf_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    set_error(buf);
+    return st;
+}
+
+ctf_status hip_fail(hipError_t e, const char* where)
+{
+    if (e == hipErrorOutOfMemory)
+        return fail(CTF_ERR_OUT_OF_MEMORY, "%s: %s", where, hipGetErrorString(e));
+    return fail(CTF_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Makes the context's device current for the scope of a call.
+struct DeviceScope {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// decoder.hip / filter_decoder.hip
+ctf_status ctf_internal_decoder_texture(ctf_texture t);
+hipError_t ctf_internal_decoder_eval(const ctf_texture_s* t, const int32_t* xy, int64_t n, float* out,
+                                     hipStream_t s);
+hipError_t ctf_internal_decoder_filter(const ctf_texture_s* t, const FilterArgs& a, hipStream_t s);
+
+extern "C" {
+
+const char* ctf_last_error(void) { return g_error.c_str(); }
+
+ctf_status ctf_create(int device, ctf_context* out)
+{
+    set_error("");
+    if (!out) return fail(CTF_ERR_INVALID_ARG, "ctf_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "ctf_create: hipGetDeviceCount");
+    if (device < 0 || device >= n)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_create: device %d not in [0, %d)", device, n);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "ctf_create: hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_create: device %d is %s, this library is built for gfx950",
+                    device, prop.gcnArchName);
+    ctf_context c = new (std::nothrow) ctf_context_s;
+    if (!c) return fail(CTF_ERR_OUT_OF_MEMORY, "ctf_create: host allocation");
+    c->device = device;
+    *out = c;
+    return CTF_OK;
+}
+
+ctf_status ctf_destroy(ctf_context ctx)
+{
+    set_error("");
+    if (!ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_destroy: NULL context");
+    delete ctx;
+    return CTF_OK;
+}
+
+ctf_status ctf_texture_create(ctf_context ctx, const ctf_texture_desc* d, ctf_texture* out)
+{
+    set_error("");
+    if (!ctx || !d || !out) return fail(CTF_ERR_INVALID_ARG, "ctf_texture_create: NULL argument");
+    *out = nullptr;
+    if (!pow2(d->width) || !pow2(d->height) || d->width > (1 << 23) || d->height > (1 << 23))
+        return fail(CTF_ERR_INVALID_ARG, "ctf_texture_create: width/height %d x %d must be powers of two <= 2^23",
+                    d->width, d->height);
+    DeviceScope ds(ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_texture_create: set device");
+
+    ctf_texture t = new (std::nothrow) ctf_texture_s;
+    if (!t) return fail(CTF_ERR_OUT_OF_MEMORY, "ctf_texture_create: host allocation");
+    t->ctx = ctx;
+    t->desc = *d;
+    DevTexture& T = t->dev;
+    std::memset(&T, 0, sizeof T);
+    T.kind = d->kind;
+    T.width = d->width;
+    T.height = d->height;
+    T.wmask = (uint32_t)d->width - 1u;
+    T.hmask = (uint32_t)d->height - 1u;
+    T.inv_w = 1.0f / (float)d->width;
+
+    ctf_status st = CTF_OK;
+    switch (d->kind) {
+    case CTF_TEX_SINUSOIDS: {
+        if (d->width != d->height) { st = fail(CTF_ERR_INVALID_ARG, "sinusoid texture must be square"); break; }
+        if (d->n_terms <= 0 || d->n_terms > 4096 || !d->pqj || !d->amp) {
+            st = fail(CTF_ERR_INVALID_ARG, "sinusoid texture: n_terms in 1..4096 and pqj/amp required");
+            break;
+        }
+        const int K = d->n_terms;
+        std::vector<int32_t> host((size_t)4 * K * 4);
+        for (int i = 0; i < 4 * K; ++i) {
+            const int32_t p = d->pqj[3 * i], q = d->pqj[3 * i + 1], j = d->pqj[3 * i + 2];
+            if (p <= -(1 << 23) || p >= (1 << 23) || q <= -(1 << 23) || q >= (1 << 23) || j < 0) {
+                st = fail(CTF_ERR_INVALID_ARG, "sinusoid term %d: |p|,|q| must be < 2^23 and j >= 0", i);
+                break;
+            }
+            float amp = d->amp[i];
+            int32_t bits;
+            std::memcpy(&bits, &amp, 4);
+            host[4 * i + 0] = p;
+            host[4 * i + 1] = q;
+            host[4 * i + 2] = j;
+            host[4 * i + 3] = bits;
+        }
+        if (st != CTF_OK) break;
+        hipError_t e = hipMalloc(&t->terms, host.size() * 4);
+        if (e == hipSuccess) e = hipMemcpy(t->terms, host.data(), host.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { st = hip_fail(e, "ctf_texture_create: terms"); break; }
+        T.n_terms = K;
+        T.terms = reinterpret_cast<const int4*>(t->terms);
+        break;
+    }
+    case CTF_TEX_AFFINE:
+        std::memcpy(T.affine, d->affine, sizeof T.affine);
+        break;
+    case CTF_TEX_CONSTANT:
+        std::memcpy(T.constant, d->constant, sizeof T.constant);
+        break;
+    case CTF_TEX_TABLE: {
+        if (!d->table) { st = fail(CTF_ERR_INVALID_ARG, "table texture: table is NULL"); break; }
+        const size_t bytes = (size_t)d->width * d->height * 16;
+        hipError_t e = hipMalloc(&t->table, bytes);
+        if (e == hipSuccess) e = hipMemcpy(t->table, d->table, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { st = hip_fail(e, "ctf_texture_create: table"); break; }
+        T.table = reinterpret_cast<const float4*>(t->table);
+        break;
+    }
+    case CTF_TEX_DECODER:
+        if (!d->decoder) { st = fail(CTF_ERR_INVALID_ARG, "decoder texture: decoder is NULL"); break; }
+        if (d->precision != CTF_FP16 && d->precision != CTF_BF16) {
+            st = fail(CTF_ERR_INVALID_ARG, "decoder texture: precision must be CTF_FP16 or CTF_BF16");
+            break;
+        }
+        st = ctf_internal_decoder_texture(t);
+        break;
+    default:
+        st = fail(CTF_ERR_INVALID_ARG, "ctf_texture_create: unknown kind %d", d->kind);
+    }
+    if (st != CTF_OK) {
+        std::string keep = g_error;
+        ctf_texture_destroy(t);
+        set_error(keep);
+        return st;
+    }
+    *out = t;
+    return CTF_OK;
+}
+
+ctf_status ctf_texture_destroy(ctf_texture t)
+{
+    if (!t) return fail(CTF_ERR_INVALID_ARG, "ctf_texture_destroy: NULL texture");
+    DeviceScope ds(t->ctx->device);
+    if (t->terms) (void)hipFree(t->terms);
+    if (t->table) (void)hipFree(t->table);
+    if (t->dec_buf) (void)hipFree(t->dec_buf);
+    delete t;
+    set_error("");
+    return CTF_OK;
+}
+
+ctf_status ctf_texture_eval(ctf_texture t, const int32_t* xy, int64_t n, float* rgba, void* stream)
+{
+    set_error("");
+    if (!t || n < 0 || (n > 0 && (!xy || !rgba)))
+        return fail(CTF_ERR_INVALID_ARG, "ctf_texture_eval: bad arguments");
+    DeviceScope ds(t->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_texture_eval: set device");
+    hipError_t e;
+    if (t->dev.kind == CTF_TEX_DECODER)
+        e = ctf_internal_decoder_eval(t, xy, n, rgba, (hipStream_t)stream);
+    else
+        e = launch_texel_eval_simt(t->dev, xy, n, rgba, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ctf_texture_eval: launch");
+    return CTF_OK;
+}
+
+ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, int32_t sw,
+                      int32_t sh, ctf_texture tex, const ctf_method* m, uint64_t seed, float* out,
+                      ctf_tile_stats* tile_stats, ctf_frame_stats* frame_stats,
+                      int32_t* debug_lists, int32_t* debug_stf, void* stream)
+{
+    set_error("");
+    if (!ctx || !uv || !uv_derivs || !tex || !m || !out)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: NULL argument");
+    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: screen %d x %d", sw, sh);
+    if (m->kind < CTF_BILINEAR4 || m->kind > CTF_MASK)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: unknown method %d", m->kind);
+    if (m->max_evals_per_lane < 1 || m->max_evals_per_lane > 4)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: max_evals_per_lane %d not in 1..4",
+                    m->max_evals_per_lane);
+    if (m->kind == CTF_MASK && m->mask_side != 16)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: mask_side %d (16 is built)", m->mask_side);
+    if (m->box_w < 0 || m->box_h < 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: negative box budget");
+    if (m->fallback != CTF_FB_STF1)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: fallback %d not built", m->fallback);
+    if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");
+    DeviceScope ds(ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter: set device");
+
+    FilterArgs a;
+    a.uv = uv;
+    a.duv = uv_derivs;
+    a.out = out;
+    a.sw = sw;
+    a.sh = sh;
+    a.tiles_x = (sw + kTile - 1) / kTile;
+    a.ntiles = (int64_t)a.tiles_x * ((sh + kTile - 1) / kTile);
+    a.method = m->kind;
+    a.box_w = m->box_w;
+    a.box_h = m->box_h;
+    a.max_evals = m->max_evals_per_lane;
+    a.seed = seed;
+    a.layer = 0;
+    a.tile_stats = tile_stats;
+    a.frame_stats = frame_stats;
+    a.lists = debug_lists;
+    a.stf_xy = debug_stf;
+    hipError_t e;
+    if (tex->dev.kind == CTF_TEX_DECODER)
+        e = ctf_internal_decoder_filter(tex, a, (hipStream_t)stream);
+    else
+        e = launch_filter_simt(a, tex->dev, (hipStream_t)stream);
+    if (e == hipErrorInvalidValue) return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: combination not built");
+    if (e != hipSuccess) return hip_fail(e, "ctf_filter: launch");
+    return CTF_OK;
+}
+
+}  // extern "C"

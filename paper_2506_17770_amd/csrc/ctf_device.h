@@ -1,0 +1,201 @@
+// ctf_device.h -- device-side building blocks for gfx950 (wave64).
+//
+// Wave primitives, the per-lane bilinear footprint, the stochastic draw and
+// the texel producers shared by every filter kernel.  Compiled with
+// -ffp-contract=off: every fused multiply-add below is written explicitly so
+// the float32 decisions are the ones the method fixes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ctf.h"
+
+namespace ctf {
+
+constexpr int kWave = 64;
+constexpr int kTile = 8;              // 8x8 pixels per wave
+constexpr int kMaxItems = CTF_MAX_ITEMS;
+constexpr float kRange = 16777216.0f; // |texel position| < 2^24
+
+// ---------------------------------------------------------------------------
+// wave primitives
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// number of set bits of m below this lane (rank of the lane in m)
+__device__ __forceinline__ int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// Cross-lane LDS hand-off inside one wave: the wave's LDS instructions
+// execute in order, so only compiler reordering has to be prevented.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly reductions over all 64 lanes (every lane gets the result).
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// per-lane footprint (Section 3 and the supplement's code listings)
+// ---------------------------------------------------------------------------
+
+struct Footprint {
+    bool active;   // finite, in-range texel position
+    bool magnify;  // both screen-axis footprints span at most one texel
+    int x0, y0;    // upper-left texel of the 2x2 footprint
+    float s, t;    // position inside the footprint, in [0,1)
+};
+
+__device__ __forceinline__ Footprint footprint(float u, float v, float4 d, float W, float H)
+{
+    Footprint f;
+    f.active = false;
+    f.magnify = false;
+    f.x0 = f.y0 = 0;
+    f.s = f.t = 0.f;
+    if (!__builtin_isfinite(u) || !__builtin_isfinite(v)) return f;
+    const float fx = __builtin_fmaf(u, W, -0.5f);
+    const float fy = __builtin_fmaf(v, H, -0.5f);
+    if (!(__builtin_fabsf(fx) < kRange) || !(__builtin_fabsf(fy) < kRange)) return f;
+    const float flx = __builtin_floorf(fx), fly = __builtin_floorf(fy);
+    f.x0 = (int)flx;
+    f.y0 = (int)fly;
+    f.s = fx - flx;
+    f.t = fy - fly;
+    f.active = true;
+    const float a = d.x * W, b = d.y * H, c = d.z * W, e = d.w * H;
+    const float rx2 = __builtin_fmaf(a, a, b * b);
+    const float ry2 = __builtin_fmaf(c, c, e * e);
+    f.magnify = (rx2 <= 1.0f) && (ry2 <= 1.0f);
+    return f;
+}
+
+// Bilinear filtering of texels v0 = (x0,y0), v1 = (x0+1,y0), v2 = (x0,y0+1),
+// v3 = (x0+1,y0+1) as two lerps in x and one in y, lerp(a, b, s) =
+// fma(s, b - a, a): weights (1-s)(1-t), s(1-t), (1-s)t, st, with constants
+// reproduced exactly.  One fixed op sequence used by every method, so exact
+// filtering gives the same bits whichever lane produced the texels.
+__device__ __forceinline__ float lerp1(float a, float b, float s)
+{
+    return __builtin_fmaf(s, b - a, a);
+}
+
+__device__ __forceinline__ float4 bilerp(float s, float t, float4 v0, float4 v1, float4 v2,
+                                         float4 v3)
+{
+    float4 r;
+    r.x = lerp1(lerp1(v0.x, v1.x, s), lerp1(v2.x, v3.x, s), t);
+    r.y = lerp1(lerp1(v0.y, v1.y, s), lerp1(v2.y, v3.y, s), t);
+    r.z = lerp1(lerp1(v0.z, v1.z, s), lerp1(v2.z, v3.z, s), t);
+    r.w = lerp1(lerp1(v0.w, v1.w, s), lerp1(v2.w, v3.w, s), t);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// one-tap STF draw [Pharr et al. 2024]: texel (x0 + [u1 < s], y0 + [u2 < t])
+// ---------------------------------------------------------------------------
+
+// The "pcg" hash of Jarzynski & Olano, "Hash Functions for GPU Rendering"
+// (JCGT 2020): an LCG step followed by PCG's RXS-M-XS output permutation.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
+{
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+__device__ __forceinline__ int2 stf_pick(const Footprint& f, uint64_t seed, uint32_t layer,
+                                         int px, int py)
+{
+    uint32_t h = pcg_hash(layer ^ (uint32_t)(seed >> 32));
+    h = pcg_hash((uint32_t)py ^ h);
+    h = pcg_hash((uint32_t)px ^ h);
+    const uint32_t h1 = pcg_hash((uint32_t)seed ^ h);
+    const uint32_t h2 = pcg_hash(h1);
+    const float u1 = (float)(h1 >> 8) * 0x1p-24f;
+    const float u2 = (float)(h2 >> 8) * 0x1p-24f;
+    return make_int2(f.x0 + (u1 < f.s ? 1 : 0), f.y0 + (u2 < f.t ? 1 : 0));
+}
+
+// ---------------------------------------------------------------------------
+// texel producers
+// ---------------------------------------------------------------------------
+
+struct DevTexture {
+    int kind;
+    int width, height;
+    uint32_t wmask, hmask;
+    float inv_w;
+    int n_terms;
+    const int4* __restrict__ terms;   // [4][K] = (p, q, j, bits of amp)
+    float affine[4][3];
+    float constant[4];
+    const float4* __restrict__ table; // [height][width]
+};
+
+// 1/2 + 1/2 sum_k a_k sin(2 pi r_k / W), r_k = (p x + q y + j) mod W.  The
+// phase is an exact integer, r/W is exact in float32, and v_sin_f32 takes
+// its argument in revolutions, so each term is one hardware sine.
+__device__ __forceinline__ float sinusoid_channel(const int4* __restrict__ tc, int K,
+                                                  uint32_t wmask, float inv_w, int xm, int ym)
+{
+    float acc = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        const int4 tk = tc[k];
+        const uint32_t r = (uint32_t)(__mul24(tk.x, xm) + __mul24(tk.y, ym) + tk.z) & wmask;
+        const float sn = __builtin_amdgcn_sinf((float)r * inv_w);
+        acc = __builtin_fmaf(__int_as_float(tk.w), sn, acc);
+    }
+    return __builtin_fmaf(0.5f, acc, 0.5f);
+}
+
+template <int KIND>
+__device__ __forceinline__ float4 texel_eval(const DevTexture& T, int x, int y)
+{
+    float4 r;
+    if constexpr (KIND == CTF_TEX_SINUSOIDS) {
+        const int xm = x & (int)T.wmask, ym = y & (int)T.wmask;
+        const int K = T.n_terms;
+        r.x = sinusoid_channel(T.terms + 0 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.y = sinusoid_channel(T.terms + 1 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.z = sinusoid_channel(T.terms + 2 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.w = sinusoid_channel(T.terms + 3 * K, K, T.wmask, T.inv_w, xm, ym);
+    } else if constexpr (KIND == CTF_TEX_AFFINE) {
+        const float fx = (float)x, fy = (float)y;
+        r.x = __builtin_fmaf(T.affine[0][2], fy, __builtin_fmaf(T.affine[0][1], fx, T.affine[0][0]));
+        r.y = __builtin_fmaf(T.affine[1][2], fy, __builtin_fmaf(T.affine[1][1], fx, T.affine[1][0]));
+        r.z = __builtin_fmaf(T.affine[2][2], fy, __builtin_fmaf(T.affine[2][1], fx, T.affine[2][0]));
+        r.w = __builtin_fmaf(T.affine[3][2], fy, __builtin_fmaf(T.affine[3][1], fx, T.affine[3][0]));
+    } else if constexpr (KIND == CTF_TEX_CONSTANT) {
+        r = make_float4(T.constant[0], T.constant[1], T.constant[2], T.constant[3]);
+    } else {  // CTF_TEX_TABLE
+        r = T.table[(size_t)(y & (int)T.hmask) * T.width + (x & (int)T.wmask)];
+    }
+    return r;
+}
+
+}  // namespace ctf

@@ -1,0 +1,68 @@
+// ctf_internal.h -- host-side structures shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "ctf.h"
+#include "ctf_device.h"
+
+namespace ctf {
+
+struct FilterArgs {
+    const float* uv;
+    const float* duv;
+    float* out;
+    int sw, sh;
+    int tiles_x;
+    int64_t ntiles;
+    int method;
+    int box_w, box_h;
+    int max_evals;
+    uint64_t seed;
+    uint32_t layer;
+    ctf_tile_stats* tile_stats;
+    ctf_frame_stats* frame_stats;
+    int32_t* lists;
+    int32_t* stf_xy;
+};
+
+// Decoder parameters in the layouts the MFMA kernels read (built once per
+// texture from the float32 master copy).  See decoder.hip.
+struct DevDecoderWeights {
+    int l0, l1, tex_w;
+    int shift0, shift1;          // log2(tex_w / l0), log2(tex_w / l1)
+    int precision;               // CTF_FP16 / CTF_BF16
+    const uint16_t* lat0;        // [l0][l0][8] half / bf16
+    const uint16_t* lat1;        // [l1][l1][8]
+    const uint16_t* w1;          // A operands, MFMA lane order (see decoder.hip)
+    const uint16_t* w2;
+    const uint16_t* w3;
+    const float* bias;           // [b1 | b2 | b3] as C-operand lane values
+};
+
+hipError_t launch_filter_simt(const FilterArgs& a, const DevTexture& T, hipStream_t s);
+hipError_t launch_texel_eval_simt(const DevTexture& T, const int32_t* xy, int64_t n, float* out,
+                                  hipStream_t s);
+
+void set_error(const std::string& msg);
+
+}  // namespace ctf
+
+struct ctf_context_s {
+    int device;
+};
+
+struct ctf_decoder_s;
+
+struct ctf_texture_s {
+    ctf_context ctx;
+    ctf_texture_desc desc;
+    ctf::DevTexture dev;
+    void* terms = nullptr;      // device int4 [4][K]
+    void* table = nullptr;      // device float4 [H][W]
+    void* dec_buf = nullptr;    // device decoder weights (one allocation)
+    ctf::DevDecoderWeights dec{};
+};

@@ -1,0 +1,453 @@
+// filter_decoder.hip -- collaborative filtering with the learned texel producer.
+//
+// Same decisions as the per-lane path (Sections 3.1-3.3, remapping and the
+// one-tap fallback), but texel production is batched: the wave writes the
+// (x, y) of every texel it must produce into an LDS row list (the unique
+// texels first, then one row per fallback draw) and decodes the rows 16 at
+// a time on MFMA (decoder_mlp.h).  Dedup therefore turns the 4-texel
+// bilinear decode into one dense MLP pass over the wave's distinct texels.
+//
+// Waves are persistent: each loads the MLP weights into registers once and
+// walks a band of tiles.  Workgroups are dispatched round-robin over the 8
+// XCDs; band b of the screen goes to the workgroups of XCD b so that the
+// latent-grid reads of neighbouring tiles share an L2.
+#include "ctf_device.h"
+#include "ctf_internal.h"
+#include "decoder_mlp.h"
+
+namespace ctf {
+
+namespace {
+
+constexpr int kDecWaves = 4;
+
+struct DecLds {
+    float4 vals[kMaxItems];
+    int2 rows[kMaxItems];
+    uint64_t keys[kMaxItems];
+    uint16_t items[kMaxItems];
+    uint8_t rank[256];
+    uint8_t bytes[256];
+};
+
+struct DecArgs {
+    const uint16_t* lat0;
+    const uint16_t* lat1;
+    const uint16_t* w;
+    const float* bias;
+    int l0, l1, shift0, shift1, tex_w;
+};
+
+__device__ int dec_list_sorted(DecLds& L, bool inA, const Footprint& f, int xmin, int ymin)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint64_t key = ~0ull;
+        if (inA)
+            key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) | (uint32_t)(f.x0 + (q & 1) - xmin);
+        L.keys[4 * lane + q] = key;
+    }
+    for (int size = 2; size <= kMaxItems; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            wave_lds_sync();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = lane + kWave * h;
+                const int i = (p / stride) * stride * 2 + (p % stride);
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint64_t x = L.keys[i], y = L.keys[j];
+                if ((x > y) == up) {
+                    L.keys[i] = y;
+                    L.keys[j] = x;
+                }
+            }
+        }
+    wave_lds_sync();
+    uint64_t k4[4];
+    bool first[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int i = kWave * c + lane;
+        k4[c] = L.keys[i];
+        first[c] = k4[c] != ~0ull && (i == 0 || L.keys[i - 1] != k4[c]);
+    }
+    wave_lds_sync();
+    int base = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t b = ballot(first[c]);
+        if (first[c]) L.keys[base + mbcnt(b)] = k4[c];
+        base += popc64(b);
+    }
+    wave_lds_sync();
+    return base;
+}
+
+__device__ __forceinline__ int dec_list_find(const DecLds& L, int n, uint64_t key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (L.keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int METHOD, int P, bool STATS>
+__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, DecArgs D)
+{
+    __shared__ DecLds lds_all[kDecWaves];
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int j = lane & 15, g = lane >> 4;
+    DecLds& L = lds_all[wid];
+
+    FwdWeights<P> W;
+    W.load(D.w, lane);
+    Biases Bz;
+    Bz.load(D.bias, lane);
+
+    // XCD-aware band of tiles for this wave
+    const int xcd = blockIdx.x & 7;
+    const int nblk_x = (int)(gridDim.x >> 3);
+    const int lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
+    const int nw = nblk_x * kDecWaves;
+    const int64_t band_b = a.ntiles * xcd / 8, band_e = a.ntiles * (xcd + 1) / 8;
+
+    for (int64_t tile = band_b + lw; tile < band_e; tile += nw) {
+        const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
+        const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+        const bool in_screen = px < a.sw && py < a.sh;
+        const int64_t pix = (int64_t)py * a.sw + px;
+        Footprint f;
+        {
+            float2 uv = make_float2(__builtin_nanf(""), 0.f);
+            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (in_screen) {
+                uv = reinterpret_cast<const float2*>(a.uv)[pix];
+                d = reinterpret_cast<const float4*>(a.duv)[pix];
+            }
+            f = footprint(uv.x, uv.y, d, (float)D.tex_w, (float)D.tex_w);
+        }
+        const bool inA = f.active && f.magnify;
+        const uint64_t act = ballot(f.active);
+        const uint64_t A = ballot(inA);
+        const int nA = popc64(A);
+
+        int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
+        constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+        if ((kCollab || STATS) && nA > 0) {
+            xmin = wave_min(inA ? f.x0 : INT32_MAX);
+            ymin = wave_min(inA ? f.y0 : INT32_MAX);
+            bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
+            bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
+        }
+        const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+
+        uint64_t B[4] = {0, 0, 0, 0};
+        int nmask = 0;
+        constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
+        if (kNeedMask && fits16) {
+            reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
+            wave_lds_sync();
+            if (inA) {
+                const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
+                L.bytes[t] = 1;
+                L.bytes[t + 1] = 1;
+                L.bytes[t + 16] = 1;
+                L.bytes[t + 17] = 1;
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int w = 0; w < 4; ++w) B[w] = ballot(L.bytes[64 * w + lane] != 0);
+            int base = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if ((B[w] >> lane) & 1u) {
+                    const int r = base + mbcnt(B[w]);
+                    L.items[r] = (uint16_t)(64 * w + lane);
+                    L.rank[64 * w + lane] = (uint8_t)r;
+                }
+                base += popc64(B[w]);
+            }
+            nmask = base;
+            wave_lds_sync();
+        }
+
+        const int k = a.max_evals;
+        int n = 0;
+        bool cap_ok = true, count_ok = true, success = false, sorted = false;
+        int unique = nmask;
+        if constexpr (METHOD == CTF_BOX) {
+            const int64_t area = (int64_t)bbw * bbh;
+            n = area > INT32_MAX ? INT32_MAX : (int)area;
+            cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
+            count_ok = area <= (int64_t)k * nA;
+            success = nA > 0 && cap_ok && count_ok;
+        } else if constexpr (METHOD == CTF_MASK) {
+            cap_ok = fits16;
+            n = fits16 ? nmask : 0;
+            count_ok = n <= k * nA;
+            success = fits16 && count_ok;
+        } else if constexpr (METHOD == CTF_LIST) {
+            if (nA > 0 && !fits16) {
+                n = dec_list_sorted(L, inA, f, xmin, ymin);
+                sorted = true;
+            } else {
+                n = nmask;
+            }
+            unique = n;
+            count_ok = n <= k * nA;
+            success = nA > 0 && count_ok;
+        }
+        if constexpr (STATS && METHOD != CTF_LIST) {
+            if (nA > 0 && !fits16) unique = dec_list_sorted(L, inA, f, xmin, ymin);
+        }
+        if (nA == 0) unique = 0;
+
+        bool exact, draws;
+        if constexpr (METHOD == CTF_BILINEAR4) {
+            exact = f.active;
+            draws = false;
+        } else if constexpr (METHOD == CTF_STF1) {
+            exact = false;
+            draws = f.active;
+        } else {
+            exact = inA && success;
+            draws = f.active && !exact;
+        }
+        const uint64_t stfmask = ballot(draws);
+        const int nstf = popc64(stfmask);
+        int2 pick = make_int2(INT32_MIN, INT32_MIN);
+        if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
+
+        // ---- row list: the texels to produce
+        const int rank_act = mbcnt(act);
+        const int ns = success ? n : 0;
+        int R;
+        if constexpr (METHOD == CTF_BILINEAR4) {
+            R = 4 * popc64(act);
+            if (f.active) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
+            }
+        } else {
+            R = ns + nstf;
+            for (int i = lane; i < ns; i += kWave) {
+                int ex, ey;
+                if constexpr (METHOD == CTF_BOX) {
+                    ex = xmin + i % bbw;
+                    ey = ymin + i / bbw;
+                } else {
+                    if (sorted) {
+                        const uint64_t key = L.keys[i];
+                        ex = xmin + (int)(uint32_t)key;
+                        ey = ymin + (int)(key >> 32);
+                    } else {
+                        const int t = L.items[i];
+                        ex = xmin + (t & 15);
+                        ey = ymin + (t >> 4);
+                    }
+                }
+                L.rows[i] = make_int2(ex, ey);
+                if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+            }
+            if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
+        }
+        wave_lds_sync();
+
+        // ---- decode the rows, 16 per MFMA tile
+        for (int r0 = 0; r0 < R; r0 += 16) {
+            const int row = r0 + j;
+            const bool valid = row < R;
+            const int2 p = valid ? L.rows[row] : make_int2(0, 0);
+            LatentTap tap;
+            const f4 X = latent_features<P>(D.lat0, D.lat1, D.l0, D.l1, D.shift0, D.shift1, D.tex_w, p.x, p.y, g, tap);
+            const f4 y = mlp_forward<P>(W, Bz, X, nullptr, nullptr);
+            if (g == 0 && valid) L.vals[row] = make_float4(y[0], y[1], y[2], y[3]);
+        }
+        wave_lds_sync();
+
+        // ---- gather and weight
+        float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (METHOD == CTF_BILINEAR4) {
+            if (exact) {
+                const int b = 4 * rank_act;
+                res = bilerp(f.s, f.t, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
+            }
+        } else {
+            if (draws) res = L.vals[ns + mbcnt(stfmask)];
+            if constexpr (kCollab) {
+                if (exact) {
+                    int idx[4];
+                    if constexpr (METHOD == CTF_BOX) {
+                        const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
+                        idx[0] = b;
+                        idx[1] = b + 1;
+                        idx[2] = b + bbw;
+                        idx[3] = b + bbw + 1;
+                    } else if (sorted) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
+                                                 (uint32_t)(f.x0 + (q & 1) - xmin);
+                            idx[q] = dec_list_find(L, n, key);
+                        }
+                    } else {
+                        const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
+                        idx[0] = L.rank[t];
+                        idx[1] = L.rank[t + 1];
+                        idx[2] = L.rank[t + 16];
+                        idx[3] = L.rank[t + 17];
+                    }
+                    res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
+                }
+            }
+        }
+        if (in_screen) {
+            reinterpret_cast<float4*>(a.out)[pix] = res;
+            if (a.stf_xy)
+                reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+        }
+        if (lane == 0) {
+            if (a.tile_stats) {
+                ctf_tile_stats S;
+                S.active = act;
+                S.part = A;
+                S.stf = stfmask;
+                for (int w = 0; w < 4; ++w) S.mask[w] = fits16 ? B[w] : 0ull;
+                S.xmin = xmin;
+                S.ymin = ymin;
+                S.bbw = bbw;
+                S.bbh = bbh;
+                S.n = n;
+                S.unique = unique;
+                S.evals = R;
+                S.flags = (success ? CTF_TILE_OK : 0) | (nA && !cap_ok ? CTF_TILE_CAP : 0) |
+                          (nA && cap_ok && !count_ok ? CTF_TILE_OVERFLOW : 0) | (nA == 0 ? CTF_TILE_EMPTY : 0);
+                for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
+                a.tile_stats[tile] = S;
+            }
+            if (a.frame_stats && act) {
+                ctf_frame_stats* F = a.frame_stats;
+                atomicAdd((unsigned long long*)&F->evals, (unsigned long long)R);
+                atomicAdd((unsigned long long*)&F->active, (unsigned long long)popc64(act));
+                atomicAdd((unsigned long long*)&F->stf, (unsigned long long)nstf);
+                atomicAdd((unsigned long long*)&F->minify, (unsigned long long)popc64(act & ~A));
+                atomicAdd((unsigned long long*)&F->tiles, 1ull);
+                atomicAdd((unsigned long long*)&F->rows, (unsigned long long)((R + 15) & ~15));
+                if (kCollab && success) atomicAdd((unsigned long long*)&F->tiles_ok, 1ull);
+                if (kCollab && nA && !success) atomicAdd((unsigned long long*)&F->tiles_fail, 1ull);
+            }
+        }
+        wave_lds_sync();  // the next tile reuses this wave's LDS slice
+    }
+}
+
+// rgba[i] = decoder(xy[i]): 16 texels per MFMA tile, persistent waves.
+template <int P>
+__global__ __launch_bounds__(256, 2) void k_decoder_eval(DecArgs D, const int2* __restrict__ xy, int64_t n,
+                                                         float4* __restrict__ out)
+{
+    const int lane = lane_id();
+    const int j = lane & 15, g = lane >> 4;
+    FwdWeights<P> W;
+    W.load(D.w, lane);
+    Biases Bz;
+    Bz.load(D.bias, lane);
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t ntiles = (n + 15) / 16;
+    for (int64_t t = gw; t < ntiles; t += nw) {
+        const int64_t row = t * 16 + j;
+        const bool valid = row < n;
+        const int2 p = valid ? xy[row] : make_int2(0, 0);
+        LatentTap tap;
+        const f4 X = latent_features<P>(D.lat0, D.lat1, D.l0, D.l1, D.shift0, D.shift1, D.tex_w, p.x, p.y, g, tap);
+        const f4 y = mlp_forward<P>(W, Bz, X, nullptr, nullptr);
+        if (g == 0 && valid) out[row] = make_float4(y[0], y[1], y[2], y[3]);
+    }
+}
+
+DecArgs dec_args(const ctf_texture_s* t)
+{
+    const DevDecoderWeights& W = t->dec;
+    DecArgs d;
+    d.lat0 = W.lat0;
+    d.lat1 = W.lat1;
+    d.w = W.w1;
+    d.bias = W.bias;
+    d.l0 = W.l0;
+    d.l1 = W.l1;
+    d.shift0 = W.shift0;
+    d.shift1 = W.shift1;
+    d.tex_w = W.tex_w;
+    return d;
+}
+
+int device_cus()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+
+template <int METHOD, int P>
+hipError_t launch_dec(const FilterArgs& a, const DecArgs& d, hipStream_t s)
+{
+    // persistent grid: up to 2 workgroups per CU, a multiple of the 8 XCDs
+    int64_t blocks = (a.ntiles + kDecWaves - 1) / kDecWaves;
+    const int64_t cap = (int64_t)device_cus() * 2;
+    if (blocks > cap) blocks = cap;
+    blocks = (blocks + 7) / 8 * 8;
+    if (a.tile_stats)
+        hipLaunchKernelGGL((k_filter_dec<METHOD, P, true>), dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    else
+        hipLaunchKernelGGL((k_filter_dec<METHOD, P, false>), dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_dec_p(const FilterArgs& a, const DecArgs& d, hipStream_t s)
+{
+    switch (a.method) {
+    case CTF_BILINEAR4: return launch_dec<CTF_BILINEAR4, P>(a, d, s);
+    case CTF_STF1: return launch_dec<CTF_STF1, P>(a, d, s);
+    case CTF_LIST: return launch_dec<CTF_LIST, P>(a, d, s);
+    case CTF_BOX: return launch_dec<CTF_BOX, P>(a, d, s);
+    case CTF_MASK: return launch_dec<CTF_MASK, P>(a, d, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+}  // namespace ctf
+
+using namespace ctf;
+
+hipError_t ctf_internal_decoder_filter(const ctf_texture_s* t, const FilterArgs& a, hipStream_t s)
+{
+    const DecArgs d = dec_args(t);
+    return t->dec.precision == CTF_BF16 ? launch_dec_p<CTF_BF16>(a, d, s) : launch_dec_p<CTF_FP16>(a, d, s);
+}
+
+hipError_t ctf_internal_decoder_eval(const ctf_texture_s* t, const int32_t* xy, int64_t n, float* out,
+                                     hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const DecArgs d = dec_args(t);
+    int64_t blocks = ((n + 15) / 16 + 3) / 4;
+    const int64_t cap = (int64_t)device_cus() * 2;
+    if (blocks > cap) blocks = cap;
+    const int2* p = reinterpret_cast<const int2*>(xy);
+    float4* o = reinterpret_cast<float4*>(out);
+    if (t->dec.precision == CTF_BF16)
+        hipLaunchKernelGGL(k_decoder_eval<CTF_BF16>, dim3((unsigned)blocks), dim3(256), 0, s, d, p, n, o);
+    else
+        hipLaunchKernelGGL(k_decoder_eval<CTF_FP16>, dim3((unsigned)blocks), dim3(256), 0, s, d, p, n, o);
+    return hipGetLastError();
+}
