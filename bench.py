@@ -1,0 +1,226 @@
+"""Benchmark: collaborative vs 4-tap bilinear filtering with a learned texel decoder.
+
+Workload (default): a 3840x2160 frame of four seeded perspective planes
+textured by a learned decoder (latent grids 512^2 and 128^2 x 8 channels,
+MLP 16-64-64-4) trained on the GPU against a 2048^2 procedural texture (32
+sinusoids per channel).  One step = one filtered frame with List-exact
+dedup (up to 4 texels per lane, so magnifying waves never overflow) and
+one-tap STF for minifying pixels; the 4-tap baseline decodes all four
+texels of every active pixel through the same MFMA decode.
+
+Prints one JSON line.  Inputs are synthetic and resident in GPU memory
+before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MLP_FLOP = 2 * (16 * 64 + 64 * 64 + 64 * 4)      # useful FLOP per decoded texel
+PEAK_FP16_TFLOPS = 2500.0                          # MI355X dense fp16/bf16 MFMA
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--width", type=int, default=3840)
+    ap.add_argument("--height", type=int, default=2160)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp16", "bf16"], default="fp16")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (scale for the HBM byte counters)")
+    return ap.parse_args()
+
+
+def timed(fn, stream, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in ev]
+    return wall, per
+
+
+def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed):
+    """Oracle (float64 decoder, List k=4) on a bounded sample of tiles, all host threads."""
+    import oracle as O
+    tiles_x = (sc.width + 7) // 8
+    ntiles = tiles_x * ((sc.height + 7) // 8)
+    otex = O.decoder_texture(tex_w, l0, l1, H, dec_params.astype(np.float64))
+    meth = O.method(O.LIST, k=4)
+    threads = os.cpu_count() or 1
+    rng = np.random.default_rng(0)
+    # calibrate on one tile row, then size the sample to the time budget
+    t0 = time.perf_counter()
+    O.filter(sc.uv, sc.duv, otex, meth, seed=seed, tiles=(ntiles // 2, ntiles // 2 + 64), stats=False)
+    per_tile = (time.perf_counter() - t0) / 64
+    n_sample = int(max(64, min(ntiles, args.cpu_seconds * threads / max(per_tile, 1e-6))))
+    starts = np.sort(rng.choice(ntiles // 64, size=max(1, n_sample // 64), replace=False)) * 64
+    chunks = np.array_split(starts, threads)
+
+    def work(ch):
+        for b in ch:
+            O.filter(sc.uv, sc.duv, otex, meth, seed=seed, tiles=(int(b), int(b) + 64), stats=False)
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(c,)) for c in chunks if len(c)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    dt = time.perf_counter() - t0
+    px = len(starts) * 64 * 64
+    return {"value": px / dt / 1e9, "unit": "Gpixels/s", "cores": len(ths), "kind": "oracle",
+            "sample": f"{len(starts) * 64} of {ntiles} 8x8 tiles of the same frame (runs of 64 tiles), "
+                      f"float64 decoder, List k=4 + STF, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import ctf_synth as cs
+    import paper_2506_17770_amd as ctf
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    prec = ctf.FP16 if args.precision == "fp16" else ctf.BF16
+    tex_w, l0, l1, H, K, F = 2048, 512, 128, 64, 32, 64
+    seed_scene, seed_tex, seed_stf, seed_dec = 1, 2, 0, 3
+
+    log("bench: generating scene")
+    sc = cs.random_planes_scene(args.width, args.height, tex_w, tex_w, seed=seed_scene)
+    ctx = ctf.Context(0)
+    pqj, amp = cs.sinusoid_params(tex_w, K, F, seed=seed_tex)
+    target = ctx.sinusoid_texture(tex_w, pqj, amp)
+    init = cs.decoder_init(l0, l1, H, seed=seed_dec)
+    dec = ctx.decoder(l0, l1, H, tex_w, init)
+
+    log(f"bench: training decoder, {args.train_steps} steps x {args.batch}")
+    trace = torch.zeros(max(1, args.train_steps), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if args.train_steps:
+        dec.train(target, args.train_steps, batch=args.batch, lr=1e-3, seed=7, precision=ctf.BF16,
+                  loss_trace=trace)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    tr = trace.cpu().numpy()
+    log(f"bench: trained in {train_s:.1f} s, final loss {tr[-1]:.3e}")
+    dtex = ctx.decoder_texture(dec, prec)
+
+    # decoder quality over the whole 2048^2 lattice vs the procedural texture
+    # (the GPU's float32 procedural texels, within 3e-7 of float64)
+    ys, xs = np.mgrid[0:tex_w, 0:tex_w]
+    xy = torch.from_numpy(np.stack([xs.ravel(), ys.ravel()], -1).astype(np.int32)).to(dev)
+    dv = dtex.eval(xy)
+    pv = target.eval(xy)
+    mse = float(((dv.double() - pv.double()) ** 2).mean())
+    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    max_abs = float((dv - pv).abs().max())
+    init_tex = ctx.decoder_texture(ctx.decoder(l0, l1, H, tex_w, init), prec)
+    mse0 = float(((init_tex.eval(xy).double() - pv.double()) ** 2).mean())
+    psnr_init = 10 * math.log10(1.0 / mse0)
+    del xy, dv, pv
+
+    uv = torch.from_numpy(sc.uv).to(dev)
+    duv = torch.from_numpy(sc.duv).to(dev)
+    out = torch.empty((args.height, args.width, 4), dtype=torch.float32, device=dev)
+    m_col = ctf.method(ctf.LIST, k=4)
+    m_b4 = ctf.method(ctf.BILINEAR4)
+
+    # statistics of the same frames (untimed runs)
+    def stats(m):
+        fs = ctf.frame_stats_buffer()
+        ctx.filter(uv, duv, dtex, m, seed=seed_stf, out=out, frame_stats=fs)
+        torch.cuda.synchronize()
+        return ctf.frame_stats_dict(fs)
+
+    s_col, s_b4 = stats(m_col), stats(m_b4)
+    npx = args.width * args.height
+
+    if args.calib_copy:
+        src = torch.ones(64 * 2**20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 268435456 bytes done")
+        del src, dst
+
+    log("bench: timing")
+    run_col = lambda: ctx.filter(uv, duv, dtex, m_col, seed=seed_stf, out=out)
+    run_b4 = lambda: ctx.filter(uv, duv, dtex, m_b4, seed=seed_stf, out=out)
+    wall_col, per_col = timed(run_col, stream, args.steps, args.warmup, torch)
+    wall_b4, per_b4 = timed(run_b4, stream, args.steps, args.warmup, torch)
+    ms_col = float(np.mean(per_col))
+    ms_b4 = float(np.mean(per_b4))
+    gpx_col = npx / (ms_col * 1e-3) / 1e9
+    gpx_b4 = npx / (ms_b4 * 1e-3) / 1e9
+
+    achieved = s_col["evals"] * MLP_FLOP / (ms_col * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP16_TFLOPS, "traffic": None,
+            "kernel": "k_filter_dec<LIST>", "work_per_launch": f"{s_col['evals']} decoded texels x {MLP_FLOP} FLOP"}
+    achieved_b4 = s_b4["evals"] * MLP_FLOP / (ms_b4 * 1e-3) / 1e12
+
+    res = {
+        "metric": "Gpixels/s + texel evals/pixel, collaborative vs 4-tap bilinear, 4K, 1 GPU",
+        "value": gpx_col, "unit": "Gpixels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_col, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp16" if prec == ctf.FP16 else "bf16", "data": "synthetic",
+        "config": {"workload": f"{args.width}x{args.height} four-plane frame, learned decoder "
+                               f"(latents {l0}^2+{l1}^2 x8, MLP 16-{H}-{H}-4) on a {tex_w}^2 texture, "
+                               "List dedup k=4 + one-tap STF vs 4-tap bilinear",
+                   "width": args.width, "height": args.height, "train_steps": args.train_steps,
+                   "batch": args.batch},
+        "texel_evals_per_pixel": s_col["evals"] / npx,
+        "bilinear4": {"gpixels_per_s": gpx_b4, "ms_per_step": ms_b4,
+                      "texel_evals_per_pixel": s_b4["evals"] / npx, "mfma_tflops": achieved_b4},
+        "speedup_vs_bilinear4": gpx_col / gpx_b4,
+        "fallback_fraction": s_col["stf"] / max(1, s_col["active"]),
+        "minify_fraction": s_col["minify"] / max(1, s_col["active"]),
+        "mlp_rows_per_pixel": s_col["rows"] / npx,
+        "decoder": {"psnr_db": psnr, "max_abs_err": max_abs, "psnr_db_untrained": psnr_init,
+                    "train_seconds": train_s, "train_final_loss": float(tr[-1]) if args.train_steps else None,
+                    "reference": "GPU float32 procedural texels (within 3e-7 of float64)"},
+        "wall_s": {"collaborative": wall_col, "bilinear4": wall_b4},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(args, sc, dec.params(), l0, l1, H, tex_w, seed_stf)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -141,6 +141,35 @@ __device__ __forceinline__ int2 stf_pick(const Footprint& f, uint64_t seed, uint
     return make_int2(f.x0 + (u1 < f.s ? 1 : 0), f.y0 + (u2 < f.t ? 1 : 0));
 }
 
+// Frame totals of one wave over all its tiles, added to the frame record
+// once at the end (one set of atomics per wave).
+struct FrameCounters {
+    uint64_t evals = 0, active = 0, stf = 0, minify = 0, tiles = 0, rows = 0, ok = 0, fail = 0;
+    __device__ __forceinline__ void add(int e, int act, int nstf, int mini, int rws, bool okk, bool fl)
+    {
+        evals += e;
+        active += act;
+        stf += nstf;
+        minify += mini;
+        rows += rws;
+        tiles += 1;
+        ok += okk;
+        fail += fl;
+    }
+    __device__ __forceinline__ void flush(ctf_frame_stats* F) const
+    {
+        if (!tiles) return;
+        atomicAdd((unsigned long long*)&F->evals, (unsigned long long)evals);
+        atomicAdd((unsigned long long*)&F->active, (unsigned long long)active);
+        atomicAdd((unsigned long long*)&F->stf, (unsigned long long)stf);
+        atomicAdd((unsigned long long*)&F->minify, (unsigned long long)minify);
+        atomicAdd((unsigned long long*)&F->tiles, (unsigned long long)tiles);
+        atomicAdd((unsigned long long*)&F->rows, (unsigned long long)rows);
+        atomicAdd((unsigned long long*)&F->tiles_ok, (unsigned long long)ok);
+        atomicAdd((unsigned long long*)&F->tiles_fail, (unsigned long long)fail);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // texel producers
 // ---------------------------------------------------------------------------

@@ -80,6 +80,7 @@ struct ctf_decoder_s {
     float* target = nullptr;
     float* partials = nullptr;     // [max waves][mlp_count]
     float* loss_part = nullptr;    // [max waves]
+    float* slices = nullptr;       // [max waves / kSlice][mlp_count + 1]
     float* loss_tmp = nullptr;     // [1]
 };
 
@@ -441,21 +442,34 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
     if (lane == 0) a.loss_part[gw] = loss;
 }
 
-// grad[mlp0 + p] = sum over waves of partials[w][p] (fixed order); loss.
-__global__ void k_reduce(const float* __restrict__ partials, int waves, int mlp_count,
-                         float* __restrict__ grad_mlp, const float* __restrict__ loss_part,
-                         float inv_count, float* __restrict__ loss_out)
+// Two-level fixed-order sum of the per-wave partials (deterministic):
+// level 1, block (x, y) sums waves [y*kSlice, (y+1)*kSlice) of parameters
+// x*256..; level 2 sums the slices.  Column mlp_count carries the loss.
+constexpr int kSlice = 32;
+
+__global__ void k_reduce1(const float* __restrict__ partials, const float* __restrict__ loss_part,
+                          int waves, int mlp_count, float* __restrict__ slices)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < mlp_count) {
-        float s = 0.f;
-        for (int w = 0; w < waves; ++w) s += partials[(int64_t)w * mlp_count + p];
-        grad_mlp[p] = s;
-    } else if (p == mlp_count) {
-        float s = 0.f;
-        for (int w = 0; w < waves; ++w) s += loss_part[w];
-        if (loss_out) loss_out[0] = s * inv_count;
-    }
+    const int w0 = blockIdx.y * kSlice, w1 = min(waves, w0 + kSlice);
+    if (p > mlp_count) return;
+    float s = 0.f;
+    if (p < mlp_count)
+        for (int w = w0; w < w1; ++w) s += partials[(int64_t)w * mlp_count + p];
+    else
+        for (int w = w0; w < w1; ++w) s += loss_part[w];
+    slices[(int64_t)blockIdx.y * (mlp_count + 1) + p] = s;
+}
+
+__global__ void k_reduce2(const float* __restrict__ slices, int nslices, int mlp_count,
+                          float* __restrict__ grad_mlp, float inv_count, float* __restrict__ loss_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > mlp_count) return;
+    float s = 0.f;
+    for (int y = 0; y < nslices; ++y) s += slices[(int64_t)y * (mlp_count + 1) + p];
+    if (p < mlp_count) grad_mlp[p] = s;
+    else if (loss_out) loss_out[0] = s * inv_count;
 }
 
 struct AdamArgs {
@@ -543,18 +557,20 @@ int train_waves(int n)
 hipError_t ensure_batch(ctf_decoder d, int32_t n)
 {
     if (n <= d->cap_batch) return hipSuccess;
-    for (void* p : {(void*)d->xy, (void*)d->target, (void*)d->partials, (void*)d->loss_part})
+    for (void* p : {(void*)d->xy, (void*)d->target, (void*)d->partials, (void*)d->loss_part, (void*)d->slices})
         if (p) (void)hipFree(p);
     d->xy = nullptr;
     d->target = nullptr;
     d->partials = nullptr;
     d->loss_part = nullptr;
+    d->slices = nullptr;
     d->cap_batch = 0;
     const int waves = train_waves(n);
     hipError_t e = hipMalloc(&d->xy, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc(&d->target, (size_t)n * 16);
     if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)waves * d->lay.mlp_count * 4);
     if (e == hipSuccess) e = hipMalloc(&d->loss_part, (size_t)waves * 4);
+    if (e == hipSuccess) e = hipMalloc(&d->slices, (size_t)((waves + 31) / 32) * (d->lay.mlp_count + 1) * 4);
     if (e == hipSuccess) d->cap_batch = n;
     return e;
 }
@@ -626,9 +642,12 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
     const int waves = train_waves(n);
     hipLaunchKernelGGL((k_train<P>), dim3(waves / kTrainWaves), dim3(64 * kTrainWaves), 0, s, a);
     const int rb = 256;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((L.mlp_count + 1 + rb - 1) / rb)), dim3(rb), 0, s,
-                       d->partials, waves, (int)L.mlp_count, grad + L.mlp0, d->loss_part,
-                       1.0f / (4.0f * (float)n), loss);
+    const int nsl = (waves + kSlice - 1) / kSlice;
+    const unsigned gx = (unsigned)((L.mlp_count + 1 + rb - 1) / rb);
+    hipLaunchKernelGGL(k_reduce1, dim3(gx, (unsigned)nsl), dim3(rb), 0, s, d->partials, d->loss_part, waves,
+                       (int)L.mlp_count, d->slices);
+    hipLaunchKernelGGL(k_reduce2, dim3(gx), dim3(rb), 0, s, d->slices, nsl, (int)L.mlp_count,
+                       grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
     return hipGetLastError();
 }
 
@@ -648,7 +667,7 @@ ctf_status ctf_decoder_destroy(ctf_decoder d)
     DeviceScope ds(d->ctx->device);
     for (void* p : {(void*)d->master, (void*)d->m, (void*)d->v, (void*)d->grad, (void*)d->lat_lp,
                     (void*)d->w_lp, (void*)d->bias_c, (void*)d->xy, (void*)d->target,
-                    (void*)d->partials, (void*)d->loss_part, (void*)d->loss_tmp})
+                    (void*)d->partials, (void*)d->loss_part, (void*)d->slices, (void*)d->loss_tmp})
         if (p) (void)hipFree(p);
     delete d;
     set_error("");

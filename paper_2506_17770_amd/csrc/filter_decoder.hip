@@ -116,6 +116,7 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, 
     const int lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
     const int nw = nblk_x * kDecWaves;
     const int64_t band_b = a.ntiles * xcd / 8, band_e = a.ntiles * (xcd + 1) / 8;
+    FrameCounters fc;
 
     for (int64_t tile = band_b + lw; tile < band_e; tile += nw) {
         const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
@@ -331,20 +332,12 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, 
                 for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
                 a.tile_stats[tile] = S;
             }
-            if (a.frame_stats && act) {
-                ctf_frame_stats* F = a.frame_stats;
-                atomicAdd((unsigned long long*)&F->evals, (unsigned long long)R);
-                atomicAdd((unsigned long long*)&F->active, (unsigned long long)popc64(act));
-                atomicAdd((unsigned long long*)&F->stf, (unsigned long long)nstf);
-                atomicAdd((unsigned long long*)&F->minify, (unsigned long long)popc64(act & ~A));
-                atomicAdd((unsigned long long*)&F->tiles, 1ull);
-                atomicAdd((unsigned long long*)&F->rows, (unsigned long long)((R + 15) & ~15));
-                if (kCollab && success) atomicAdd((unsigned long long*)&F->tiles_ok, 1ull);
-                if (kCollab && nA && !success) atomicAdd((unsigned long long*)&F->tiles_fail, 1ull);
-            }
         }
+        if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), (R + 15) & ~15, kCollab && success,
+                        kCollab && nA && !success);
         wave_lds_sync();  // the next tile reuses this wave's LDS slice
     }
+    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
 
 // rgba[i] = decoder(xy[i]): 16 texels per MFMA tile, persistent waves.
