@@ -52,6 +52,31 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ["paper_2506_17770_amd/csrc/filter_decoder.hip", "paper_2506_17770_amd/csrc/decoder_mlp.h",
+                  "paper_2506_17770_amd/csrc/ctf_device.h", "paper_2506_17770_amd/csrc/ctf_internal.h"]
+TRAFFIC_RECORD = "profiles/k_filter_dec_list_fp16_4k.json"
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the List kernel from the committed rocprofv3
+    counter record, or None if the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_RECORD)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"]) * 1024
+
+
 def timed(fn, stream, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -189,7 +214,8 @@ def main():
 
     achieved = s_col["evals"] * MLP_FLOP / (ms_col * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP16_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP16_TFLOPS, "traffic": measured_traffic(),
+            "algorithmic_bytes": npx * 40,
             "kernel": "k_filter_dec<LIST>", "work_per_launch": f"{s_col['evals']} decoded texels x {MLP_FLOP} FLOP"}
     achieved_b4 = s_b4["evals"] * MLP_FLOP / (ms_b4 * 1e-3) / 1e12
 

@@ -194,6 +194,25 @@ ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
                       ctf_frame_stats *frame_stats, int32_t *debug_lists, int32_t *debug_stf,
                       void *stream);
 
+/* Filter n_layers material layers of one frame in one launch.  Layer l
+ * samples texs[l] at the layer coordinates uv_l = M_l uv, where M_l =
+ * xforms[4l..4l+3] is a row-major 2x2 matrix applied to uv and to both
+ * derivative vectors in float32 as u' = fma(m01, v, m00 u), v' = fma(m11, v,
+ * m10 u); the STF draw of layer l hashes (seed, pixel, layer l).  Every
+ * texture must be a CTF_TEX_DECODER texture of the same precision; 1 <=
+ * n_layers <= 8.
+ * xforms: host float [n_layers][4]; texs: host array of n_layers handles.
+ * out: device float [n_layers][sh][sw][4].  tile_stats: nullable device
+ * [n_layers][tiles]; debug_stf: nullable device int32 [n_layers][sh][sw][2];
+ * frame_stats: nullable, totals over all layers.  Other arguments as for
+ * ctf_filter.  Errors: CTF_ERR_INVALID_ARG, CTF_ERR_UNSUPPORTED (non-decoder
+ * texture, mixed precisions, fallback other than CTF_FB_STF1). */
+ctf_status ctf_filter_layers(ctf_context ctx, const float *uv, const float *uv_derivs,
+                             int32_t sw, int32_t sh, int32_t n_layers, const ctf_texture *texs,
+                             const float *xforms, const ctf_method *method, uint64_t seed,
+                             float *out, ctf_tile_stats *tile_stats, ctf_frame_stats *frame_stats,
+                             int32_t *debug_stf, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned decoder (texel producer): latent grids + MLP
  * ------------------------------------------------------------------------- */

@@ -86,7 +86,8 @@ def lib():
         L.ctfo_filter.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.POINTER(Texture),
                                   ctypes.POINTER(Method), ctypes.c_uint64, ctypes.c_int32,
-                                  P, P, P, P, ctypes.c_int64, ctypes.c_int64]
+                                  P, P, P, P, P, ctypes.c_int64, ctypes.c_int64]
+        L.ctfo_cplus_target.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ctfo_decoder_loss_grad.argtypes = [ctypes.POINTER(Decoder), P, P, ctypes.c_int64,
                                              P, P]
         _lib = L
@@ -107,6 +108,11 @@ def pcg_hash(v: int) -> int:
 
 def _mask4(B) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(B, dtype=np.uint64).reshape(4))
+
+
+def cplus_target(nA: int, ns: int, c: int) -> int:
+    """Eq. 2: rank of the lane whose footprint spare lane c draws from."""
+    return lib().ctfo_cplus_target(nA, ns, c)
 
 
 def bit_select(B, i: int) -> int:
@@ -200,12 +206,14 @@ def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1) -> Method:
 
 
 def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 8),
-           tiles=None, stats=True, lists=False, stf=False):
+           tiles=None, stats=True, lists=False, stf=False, xform=None):
     """Run the oracle filter.  Returns dict(out f64 [H][W][4], stats, lists, stf).
 
     ``tiles`` = (begin, end) restricts the work to a tile range (the other
-    pixels of ``out`` are left zero).
+    pixels of ``out`` are left zero).  ``xform`` = 2x2 matrix of a material
+    layer applied (in float32) to uv and its derivatives.
     """
+    xf = None if xform is None else np.ascontiguousarray(np.asarray(xform, np.float32).reshape(4))
     uv = np.ascontiguousarray(uv, dtype=np.float32)
     duv = np.ascontiguousarray(duv, dtype=np.float32)
     sh, sw = uv.shape[:2]
@@ -217,7 +225,7 @@ def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 
     sx = np.full((sh, sw, 2), np.iinfo(np.int32).min, np.int32) if stf else None
     b, e = tiles if tiles is not None else (0, ntiles)
     rc = lib().ctfo_filter(_ptr(uv), _ptr(duv), sw, sh, tw, th, ctypes.byref(tex.struct),
-                           ctypes.byref(meth), seed & (2**64 - 1), layer, _ptr(out), _ptr(st),
+                           ctypes.byref(meth), seed & (2**64 - 1), layer, _ptr(xf), _ptr(out), _ptr(st),
                            _ptr(li), _ptr(sx), b, e)
     if rc:
         raise RuntimeError(f"ctfo_filter failed ({rc})")

@@ -132,6 +132,8 @@ int ctfo_texel_eval(const ctfo_texture *tex, const int32_t *xy, int64_t n, doubl
  * Minification: a lane is magnifying when both screen-axis footprints span
  * at most one texel (squared lengths <= 1).
  * ---------------------------------------------------------------------- */
+typedef struct { int32_t x, y; } texel_t;
+
 typedef struct {
     int in_screen, active, magnify;
     int px, py;
@@ -174,26 +176,59 @@ static void bilinear_weights(float s, float t, double w[4])
 /* One-tap STF draw: texel (x0 + [u1 < s], y0 + [u2 < t]) with u1, u2 24-bit
  * uniforms from the hash of (seed, layer, pixel).  Picks texel k with
  * probability equal to its bilinear weight (to 2^-24). */
-static void stf_pick(const lane_t *L, uint64_t seed, int32_t layer, int32_t out[2])
+static void stf_hashes(const lane_t *L, uint64_t seed, int32_t layer, uint32_t h[3])
 {
     uint32_t lo = (uint32_t)seed, hi = (uint32_t)(seed >> 32);
-    uint32_t h = ctfo_pcg_hash((uint32_t)layer ^ hi);
-    h = ctfo_pcg_hash((uint32_t)L->py ^ h);
-    h = ctfo_pcg_hash((uint32_t)L->px ^ h);
-    uint32_t h1 = ctfo_pcg_hash(lo ^ h);
-    uint32_t h2 = ctfo_pcg_hash(h1);
-    float u1 = (float)(h1 >> 8) * 0x1p-24f;
-    float u2 = (float)(h2 >> 8) * 0x1p-24f;
-    out[0] = L->x0 + (u1 < L->s ? 1 : 0);
-    out[1] = L->y0 + (u2 < L->t ? 1 : 0);
+    uint32_t g = ctfo_pcg_hash((uint32_t)layer ^ hi);
+    g = ctfo_pcg_hash((uint32_t)L->py ^ g);
+    g = ctfo_pcg_hash((uint32_t)L->px ^ g);
+    h[0] = ctfo_pcg_hash(lo ^ g);
+    h[1] = ctfo_pcg_hash(h[0]);
+    h[2] = ctfo_pcg_hash(h[1]);   /* third draw: the C+ spare-lane choice */
+}
+
+static float unit24(uint32_t h) { return (float)(h >> 8) * 0x1p-24f; }
+
+static void stf_pick(const lane_t *L, uint64_t seed, int32_t layer, int32_t out[2])
+{
+    uint32_t h[3];
+    stf_hashes(L, seed, layer, h);
+    out[0] = L->x0 + (unit24(h[0]) < L->s ? 1 : 0);
+    out[1] = L->y0 + (unit24(h[1]) < L->t ? 1 : 0);
+}
+
+/* Eq. 2 for a wave of nA participating lanes of which ns produce the
+ * distinct one-tap texels: spare lane of rank c in [ns, nA) adds a texel of
+ * the footprint of the lane of rank round((nA-1)(c-ns)/(nA-1-ns)) (ties up);
+ * a single spare lane maps to rank 0. */
+int ctfo_cplus_target(int32_t nA, int32_t ns, int32_t c)
+{
+    const int span = nA - 1 - ns;
+    if (span <= 0) return 0;
+    return (2 * (nA - 1) * (c - ns) + span) / (2 * span);
+}
+
+/* float32 bilinear weights, for the fallback's discrete choices */
+static void weights32(float s, float t, float w[4])
+{
+    const float is = 1.0f - s, it = 1.0f - t;
+    w[0] = is * it;
+    w[1] = s * it;
+    w[2] = is * t;
+    w[3] = s * t;
+}
+
+static int texel_in(const texel_t *set, int n, int32_t x, int32_t y)
+{
+    for (int i = 0; i < n; ++i)
+        if (set[i].x == x && set[i].y == y) return 1;
+    return 0;
 }
 
 /* ------------------------------------------------------------------------
  * Exact unique set of the footprint texels of the lanes in A, as keys
  * sorted by (y, x): plain collect, sort, drop duplicates.
  * ---------------------------------------------------------------------- */
-typedef struct { int32_t x, y; } texel_t;
-
 static int cmp_texel(const void *a, const void *b)
 {
     const texel_t *p = (const texel_t *)a, *q = (const texel_t *)b;
@@ -232,17 +267,30 @@ static int popcount64(uint64_t v)
  * The filter.  Tiles are tile_w x tile_h pixels, one wave each, lane =
  * tile_w * ly + lx, tiles row-major over the screen.
  * ---------------------------------------------------------------------- */
+/* A material layer's coordinates: uv' = M uv and the same for each of the
+ * two derivative vectors, in float32 with one fixed operation order. */
+static void layer_transform(const float *M, const float *uv, const float *duv, float uv_out[2],
+                            float duv_out[4])
+{
+    uv_out[0] = fmaf(M[1], uv[1], M[0] * uv[0]);
+    uv_out[1] = fmaf(M[3], uv[1], M[2] * uv[0]);
+    duv_out[0] = fmaf(M[1], duv[1], M[0] * duv[0]);
+    duv_out[1] = fmaf(M[3], duv[1], M[2] * duv[0]);
+    duv_out[2] = fmaf(M[1], duv[3], M[0] * duv[2]);
+    duv_out[3] = fmaf(M[3], duv[3], M[2] * duv[2]);
+}
+
 int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 int32_t tile_w, int32_t tile_h,
                 const ctfo_texture *tex, const ctfo_method *m,
-                uint64_t seed, int32_t layer,
+                uint64_t seed, int32_t layer, const float *xform,
                 double *out, ctfo_tile_stats *stats, int32_t *lists, int32_t *stf_xy,
                 int64_t tile_begin, int64_t tile_end)
 {
     if (!uv || !duv || !tex || !m || !out) return 1;
     if (sw <= 0 || sh <= 0 || tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > MAX_LANES) return 1;
     if (m->max_evals_per_lane < 1 || m->max_evals_per_lane > 4) return 1;
-    if (m->fallback != CTFO_FB_STF1) return 2;
+    if (m->fallback < CTFO_FB_STF1 || m->fallback > CTFO_FB_CPLUS) return 1;
     const int32_t W = tex->width, H = tex->height;
     const int nl = tile_w * tile_h;
     const int64_t tiles_x = (sw + tile_w - 1) / tile_w;
@@ -263,7 +311,13 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             L->active = L->magnify = 0;
             if (L->in_screen) {
                 int64_t p = (int64_t)L->py * sw + L->px;
-                footprint(uv + 2 * p, duv + 4 * p, W, H, L);
+                if (xform) {
+                    float luv[2], lduv[4];
+                    layer_transform(xform, uv + 2 * p, duv + 4 * p, luv, lduv);
+                    footprint(luv, lduv, W, H, L);
+                } else {
+                    footprint(uv + 2 * p, duv + 4 * p, W, H, L);
+                }
                 for (int c = 0; c < 4; ++c) out[4 * p + c] = 0.0;
                 if (stf_xy) stf_xy[2 * p] = stf_xy[2 * p + 1] = INT32_MIN;
             }
@@ -354,9 +408,82 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             return 1;
         }
 
-        /* steps 4-6: produce, gather and weight; fallback lanes draw one texel */
+        /* Fallback of the lanes of A when the wave fails (Section 3.4):
+         * C: every lane of A produces its one-tap texel; C+: the distinct
+         * one-tap texels (mask S, one bit per lane) are produced once and the
+         * remaining lanes of A produce extra texels (Eq. 2); both weight the
+         * produced texels of each footprint with Eq. 1.  C+ needs the wave
+         * box to fit the 16x16 mask, otherwise C is used. */
+        int fb = CTFO_FB_STF1;
+        if (!success && nA > 0 && (m->kind == CTFO_LIST || m->kind == CTFO_BOX || m->kind == CTFO_MASK))
+            fb = m->fallback;
+        if (fb == CTFO_FB_CPLUS && !fits16) fb = CTFO_FB_C;
+        texel_t prod[2 * MAX_LANES];
+        int nprod = 0, fb_evals = 0;
+        if (fb == CTFO_FB_C) {
+            for (int l = 0; l < nl; ++l) {
+                if (!((A >> l) & 1u)) continue;
+                int32_t pk[2];
+                stf_pick(&lanes[l], seed, layer, pk);
+                prod[nprod].x = pk[0];
+                prod[nprod].y = pk[1];
+                ++nprod;
+            }
+            fb_evals = nA;
+        } else if (fb == CTFO_FB_CPLUS) {
+            uint64_t Sm[4] = {0, 0, 0, 0};
+            int rank_lane[MAX_LANES];
+            int r = 0;
+            for (int l = 0; l < nl; ++l) {
+                if (!((A >> l) & 1u)) continue;
+                rank_lane[r++] = l;
+                int32_t pk[2];
+                stf_pick(&lanes[l], seed, layer, pk);
+                int t = 16 * (int)(pk[1] - ymin) + (int)(pk[0] - xmin);
+                Sm[t >> 6] |= 1ull << (t & 63);
+            }
+            const int ns = popcount64(Sm[0]) + popcount64(Sm[1]) + popcount64(Sm[2]) + popcount64(Sm[3]);
+            for (int i = 0; i < ns; ++i) {           /* item i made by the lane of rank i */
+                int t = ctfo_bit_select(Sm, i);
+                prod[nprod].x = (int32_t)(xmin + (t & 15));
+                prod[nprod].y = (int32_t)(ymin + (t >> 4));
+                ++nprod;
+            }
+            fb_evals = ns;
+            for (int c = ns; c < nA; ++c) {           /* spare lanes, Eq. 2 */
+                const int tr = ctfo_cplus_target(nA, ns, c);
+                const lane_t *T = &lanes[rank_lane[tr]];
+                float w[4];
+                weights32(T->s, T->t, w);
+                int cand[4], nc = 0;
+                float wsum = 0.0f;
+                for (int q = 0; q < 4; ++q) {
+                    const int tq = 16 * (int)(T->y0 + (q >> 1) - ymin) + (int)(T->x0 + (q & 1) - xmin);
+                    if (w[q] > 0.0f && !bit_of(Sm, tq)) {
+                        cand[nc++] = q;
+                        wsum += w[q];
+                    }
+                }
+                if (nc == 0) continue;
+                uint32_t h[3];
+                stf_hashes(&lanes[rank_lane[c]], seed, layer, h);
+                const float thr = unit24(h[2]) * wsum;
+                int pickq = cand[nc - 1];
+                float run = 0.0f;
+                for (int k = 0; k < nc; ++k) {
+                    run += w[cand[k]];
+                    if (run > thr) { pickq = cand[k]; break; }
+                }
+                prod[nprod].x = T->x0 + (pickq & 1);
+                prod[nprod].y = T->y0 + (pickq >> 1);
+                ++nprod;
+                ++fb_evals;
+            }
+        }
+
+        /* steps 4-6: produce, gather and weight; other non-exact lanes draw one texel */
         uint64_t stfmask = 0;
-        int64_t evals = 0;
+        int64_t evals = fb_evals;
         for (int l = 0; l < nl; ++l) {
             const lane_t *L = &lanes[l];
             if (!L->active) continue;
@@ -366,6 +493,37 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             if (m->kind == CTFO_BILINEAR4) exact = 1;
             else if (m->kind == CTFO_STF1) exact = 0;
             else exact = ((A >> l) & 1u) && success;
+            if (!exact && fb != CTFO_FB_STF1 && ((A >> l) & 1u)) {
+                /* Eq. 1 over the produced texels of this footprint with a
+                 * nonzero (float32) weight */
+                float w32[4];
+                double w[4], f[4], acc[4] = {0, 0, 0, 0}, sum[4] = {0, 0, 0, 0}, wsum = 0.0;
+                int N = 0;
+                weights32(L->s, L->t, w32);
+                bilinear_weights(L->s, L->t, w);
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t x = L->x0 + (q & 1), y = L->y0 + (q >> 1);
+                    if (!(w32[q] > 0.0f) || !texel_in(prod, nprod, x, y)) continue;
+                    texel_value(tex, x, y, f);
+                    for (int c = 0; c < 4; ++c) {
+                        acc[c] += w[q] * f[c];
+                        sum[c] += f[c];
+                    }
+                    wsum += w[q];
+                    ++N;
+                }
+                int32_t pick[2];
+                stf_pick(L, seed, layer, pick);
+                if (N == 0) {   /* only if the drawn texel's float32 weight underflowed */
+                    texel_value(tex, pick[0], pick[1], f);
+                    for (int c = 0; c < 4; ++c) o[c] = f[c];
+                } else {
+                    for (int c = 0; c < 4; ++c) o[c] = acc[c] + (1.0 - wsum) * sum[c] / N;
+                }
+                if (stf_xy) { stf_xy[2 * p] = pick[0]; stf_xy[2 * p + 1] = pick[1]; }
+                stfmask |= 1ull << l;
+                continue;
+            }
             if (exact) {
                 double w[4], f[4];
                 bilinear_weights(L->s, L->t, w);

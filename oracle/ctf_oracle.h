@@ -79,11 +79,15 @@ int ctfo_bit_select(const uint64_t B[4], int32_t i);   /* h(i,B) */
 int ctfo_bit_rank(const uint64_t B[4], int32_t t);     /* h^-1(t,B) */
 
 int ctfo_texel_eval(const ctfo_texture *tex, const int32_t *xy, int64_t n, double *rgba);
+int ctfo_cplus_target(int32_t nA, int32_t ns, int32_t c);   /* Eq. 2 */
 
+/* xform: nullable 2x2 row-major matrix M applied to uv and to each
+ * derivative pair before the footprint (a material layer's texture
+ * coordinates), in float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u). */
 int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 int32_t tile_w, int32_t tile_h,
                 const ctfo_texture *tex, const ctfo_method *m,
-                uint64_t seed, int32_t layer,
+                uint64_t seed, int32_t layer, const float *xform,
                 double *out, ctfo_tile_stats *stats, int32_t *lists, int32_t *stf_xy,
                 int64_t tile_begin, int64_t tile_end);
 

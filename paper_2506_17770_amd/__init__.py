@@ -71,6 +71,7 @@ SIGNATURES = {
     "ctf_texture_destroy": (_I32, [_P]),
     "ctf_texture_eval": (_I32, [_P, _P, _I64, _P, _P]),
     "ctf_filter": (_I32, [_P, _P, _P, _I32, _I32, _P, _P, _U64, _P, _P, _P, _P, _P, _P]),
+    "ctf_filter_layers": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _U64, _P, _P, _P, _P, _P]),
     "ctf_decoder_param_count": (_SZ, [_P]),
     "ctf_decoder_create": (_I32, [_P, _P, _P, _P]),
     "ctf_decoder_destroy": (_I32, [_P]),
@@ -87,7 +88,7 @@ SIGNATURES = {
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2506_17770_amd.build` (no CPU fallback exists)")
+                          "`python paper_2506_17770_amd/build.py` (no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(L, name)
@@ -197,6 +198,24 @@ class Context:
                               ctypes.byref(meth), seed & (2**64 - 1), _dptr(out),
                               _dptr(tile_stats), _dptr(frame_stats), _dptr(lists), _dptr(stf),
                               _stream(stream)))
+        return out
+
+    def filter_layers(self, uv, duv, texs, xforms, meth: Method, seed=0, out=None, tile_stats=None,
+                      frame_stats=None, stf=None, stream=None):
+        """ctf_filter_layers: one launch over len(texs) material layers.
+
+        xforms: [L][2][2] (layer uv = M uv); out: [L][H][W][4]."""
+        sh, sw = uv.shape[:2]
+        n = len(texs)
+        xf = np.ascontiguousarray(np.asarray(xforms, dtype=np.float32).reshape(n, 4))
+        handles = (ctypes.c_void_p * n)(*[t.handle.value for t in texs])
+        if out is None:
+            import torch
+            out = torch.empty((n, sh, sw, 4), dtype=torch.float32, device=uv.device)
+        _check(lib.ctf_filter_layers(self.handle, _dptr(uv), _dptr(duv), sw, sh, n, handles,
+                                     xf.ctypes.data, ctypes.byref(meth), seed & (2**64 - 1),
+                                     _dptr(out), _dptr(tile_stats), _dptr(frame_stats), _dptr(stf),
+                                     _stream(stream)))
         return out
 
     def decoder(self, l0, l1, hidden, tex_w, init, channels=8) -> "Decoder":

@@ -1,6 +1,8 @@
 """Build libctf.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2506_17770_amd.build
+    python paper_2506_17770_amd/build.py
+
+(run by path: importing the package loads the library this script builds)
 """
 from __future__ import annotations
 

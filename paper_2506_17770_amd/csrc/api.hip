@@ -3,6 +3,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -66,6 +67,8 @@ ctf_status ctf_internal_decoder_texture(ctf_texture t);
 hipError_t ctf_internal_decoder_eval(const ctf_texture_s* t, const int32_t* xy, int64_t n, float* out,
                                      hipStream_t s);
 hipError_t ctf_internal_decoder_filter(const ctf_texture_s* t, const FilterArgs& a, hipStream_t s);
+hipError_t ctf_internal_filter_layers(const ctf_texture_s* const* texs, const float* xforms, int n,
+                                      const FilterArgs& a, hipStream_t s);
 
 extern "C" {
 
@@ -222,32 +225,26 @@ ctf_status ctf_texture_eval(ctf_texture t, const int32_t* xy, int64_t n, float* 
     return CTF_OK;
 }
 
-ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, int32_t sw,
-                      int32_t sh, ctf_texture tex, const ctf_method* m, uint64_t seed, float* out,
-                      ctf_tile_stats* tile_stats, ctf_frame_stats* frame_stats,
-                      int32_t* debug_lists, int32_t* debug_stf, void* stream)
+static ctf_status check_method(const ctf_method* m, const char* who)
 {
-    set_error("");
-    if (!ctx || !uv || !uv_derivs || !tex || !m || !out)
-        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: NULL argument");
-    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: screen %d x %d", sw, sh);
     if (m->kind < CTF_BILINEAR4 || m->kind > CTF_MASK)
-        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: unknown method %d", m->kind);
+        return fail(CTF_ERR_INVALID_ARG, "%s: unknown method %d", who, m->kind);
     if (m->max_evals_per_lane < 1 || m->max_evals_per_lane > 4)
-        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: max_evals_per_lane %d not in 1..4",
-                    m->max_evals_per_lane);
+        return fail(CTF_ERR_INVALID_ARG, "%s: max_evals_per_lane %d not in 1..4", who, m->max_evals_per_lane);
     if (m->kind == CTF_MASK && m->mask_side != 16)
-        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: mask_side %d (16 is built)", m->mask_side);
-    if (m->box_w < 0 || m->box_h < 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: negative box budget");
-    if (m->fallback != CTF_FB_STF1)
-        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: fallback %d not built", m->fallback);
-    if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");
-    DeviceScope ds(ctx->device);
-    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter: set device");
+        return fail(CTF_ERR_UNSUPPORTED, "%s: mask_side %d (16 is built)", who, m->mask_side);
+    if (m->box_w < 0 || m->box_h < 0) return fail(CTF_ERR_INVALID_ARG, "%s: negative box budget", who);
+    if (m->fallback != CTF_FB_STF1) return fail(CTF_ERR_UNSUPPORTED, "%s: fallback %d not built", who, m->fallback);
+    return CTF_OK;
+}
 
+static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int32_t sh, const ctf_method* m,
+                              uint64_t seed, float* out, ctf_tile_stats* ts, ctf_frame_stats* fs, int32_t* lists,
+                              int32_t* stf)
+{
     FilterArgs a;
     a.uv = uv;
-    a.duv = uv_derivs;
+    a.duv = duv;
     a.out = out;
     a.sw = sw;
     a.sh = sh;
@@ -259,10 +256,58 @@ ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, 
     a.max_evals = m->max_evals_per_lane;
     a.seed = seed;
     a.layer = 0;
-    a.tile_stats = tile_stats;
-    a.frame_stats = frame_stats;
-    a.lists = debug_lists;
-    a.stf_xy = debug_stf;
+    a.tile_stats = ts;
+    a.frame_stats = fs;
+    a.lists = lists;
+    a.stf_xy = stf;
+    return a;
+}
+
+ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_derivs, int32_t sw, int32_t sh,
+                             int32_t n_layers, const ctf_texture* texs, const float* xforms,
+                             const ctf_method* m, uint64_t seed, float* out, ctf_tile_stats* tile_stats,
+                             ctf_frame_stats* frame_stats, int32_t* debug_stf, void* stream)
+{
+    set_error("");
+    if (!ctx || !uv || !uv_derivs || !texs || !xforms || !m || !out)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: NULL argument");
+    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: screen %d x %d", sw, sh);
+    if (n_layers < 1 || n_layers > 8) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: n_layers %d", n_layers);
+    ctf_status st = check_method(m, "ctf_filter_layers");
+    if (st != CTF_OK) return st;
+    for (int l = 0; l < n_layers; ++l) {
+        if (!texs[l] || texs[l]->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: texture %d", l);
+        if (texs[l]->dev.kind != CTF_TEX_DECODER || texs[l]->dec.precision != texs[0]->dec.precision)
+            return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: layer %d is not a decoder texture of the common precision", l);
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(xforms[4 * l + k])) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: xform %d", l);
+    }
+    DeviceScope ds(ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter_layers: set device");
+    const FilterArgs a = filter_args(uv, uv_derivs, sw, sh, m, seed, out, tile_stats, frame_stats, nullptr, debug_stf);
+    const hipError_t e = ctf_internal_filter_layers(texs, xforms, n_layers, a, (hipStream_t)stream);
+    if (e == hipErrorInvalidValue) return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: combination not built");
+    if (e != hipSuccess) return hip_fail(e, "ctf_filter_layers: launch");
+    return CTF_OK;
+}
+
+ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, int32_t sw,
+                      int32_t sh, ctf_texture tex, const ctf_method* m, uint64_t seed, float* out,
+                      ctf_tile_stats* tile_stats, ctf_frame_stats* frame_stats,
+                      int32_t* debug_lists, int32_t* debug_stf, void* stream)
+{
+    set_error("");
+    if (!ctx || !uv || !uv_derivs || !tex || !m || !out)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: NULL argument");
+    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: screen %d x %d", sw, sh);
+    ctf_status st = check_method(m, "ctf_filter");
+    if (st != CTF_OK) return st;
+    if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");
+    DeviceScope ds(ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter: set device");
+
+    const FilterArgs a = filter_args(uv, uv_derivs, sw, sh, m, seed, out, tile_stats, frame_stats, debug_lists,
+                                     debug_stf);
     hipError_t e;
     if (tex->dev.kind == CTF_TEX_DECODER)
         e = ctf_internal_decoder_filter(tex, a, (hipStream_t)stream);

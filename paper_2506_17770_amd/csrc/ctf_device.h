@@ -44,20 +44,31 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly reductions over all 64 lanes (every lane gets the result).
-__device__ __forceinline__ int wave_min(int v)
+// Wave-wide min / max (all 64 lanes must be active): DPP exchanges reduce
+// each row of 16 lanes (quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror), then the four row results are read with
+// v_readlane and combined as scalars.  The result is wave-uniform.
+template <class Op>
+__device__ __forceinline__ int wave_reduce(int v, Op op)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return op(op(r0, r1), op(r2, r3));
 }
 
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
-}
+struct MinOp {
+    __device__ __forceinline__ int operator()(int a, int b) const { return a < b ? a : b; }
+};
+struct MaxOp {
+    __device__ __forceinline__ int operator()(int a, int b) const { return a > b ? a : b; }
+};
+
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce(v, MinOp()); }
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce(v, MaxOp()); }
 
 // ---------------------------------------------------------------------------
 // per-lane footprint (Section 3 and the supplement's code listings)

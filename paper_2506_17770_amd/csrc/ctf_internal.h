@@ -8,6 +8,7 @@
 
 #include "ctf.h"
 #include "ctf_device.h"
+#include "decoder_mlp.h"
 
 namespace ctf {
 
@@ -30,17 +31,12 @@ struct FilterArgs {
 };
 
 // Decoder parameters in the layouts the MFMA kernels read (built once per
-// texture from the float32 master copy).  See decoder.hip.
+// texture from the float32 master copy; see decoder_mlp.h).
 struct DevDecoderWeights {
-    int l0, l1, tex_w;
-    int shift0, shift1;          // log2(tex_w / l0), log2(tex_w / l1)
+    LatentGrid grid;             // latents, 16-bit, both levels
     int precision;               // CTF_FP16 / CTF_BF16
-    const uint16_t* lat0;        // [l0][l0][8] half / bf16
-    const uint16_t* lat1;        // [l1][l1][8]
-    const uint16_t* w1;          // A operands, MFMA lane order (see decoder.hip)
-    const uint16_t* w2;
-    const uint16_t* w3;
-    const float* bias;           // [b1 | b2 | b3] as C-operand lane values
+    const uint16_t* w;           // packed A-operand weight blocks
+    const float* bias;           // packed C-operand biases
 };
 
 hipError_t launch_filter_simt(const FilterArgs& a, const DevTexture& T, hipStream_t s);

@@ -6,7 +6,8 @@
 //              and their targets from a texel producer;
 //   k_train    forward + backward on MFMA for 16-sample tiles (operands in
 //              bf16 or fp16, float32 accumulation), latent gradients
-//              scattered with float atomics, per-wave partial sums of the
+//              scattered as 64-bit fixed-point atomics (order independent,
+//              so training is bitwise reproducible), per-wave partial sums of the
 //              MLP weight gradients (batch reductions on MFMA after an LDS
 //              transpose of each 16x16 block);
 //   k_reduce   fixed-order sum of the partials (deterministic) and the loss;
@@ -67,7 +68,8 @@ struct ctf_decoder_s {
     float* master = nullptr;   // [total]
     float* m = nullptr;        // Adam first moment [total]
     float* v = nullptr;        // Adam second moment [total]
-    float* grad = nullptr;     // [total]
+    float* grad = nullptr;     // [total]; the latent part is filled from glat_fx
+    int64_t* glat_fx = nullptr;  // latent gradient, fixed point (2^-44 units) [mlp0]
     int64_t step = 0;
     // low-precision training copies
     int lp_precision = -1;
@@ -186,6 +188,24 @@ __global__ void k_fill(float* __restrict__ p, int64_t n, float v)
         p[i] = v;
 }
 
+// Latent gradients are summed as 64-bit fixed-point integers (units of
+// 2^-44): integer addition is associative, so the scattered sums -- and the
+// whole training run -- do not depend on the order of the atomics.
+constexpr float kFxScale = 17592186044416.0f;        // 2^44
+constexpr float kFxInv = 1.0f / 17592186044416.0f;   // 2^-44
+
+__global__ void k_zero64(int64_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_fx_to_float(const int64_t* __restrict__ fx, int64_t n, float* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)fx[i] * kFxInv;
+}
+
 template <int TEX>
 __global__ void k_sample(DevTexture T, uint64_t seed, uint32_t step, int batch, int tex_w,
                          int2* __restrict__ xy, float4* __restrict__ target)
@@ -202,16 +222,15 @@ __global__ void k_sample(DevTexture T, uint64_t seed, uint32_t step, int batch, 
 }
 
 struct TrainArgs {
-    const uint16_t* lat0;
-    const uint16_t* lat1;
+    LatentGrid grid;          // low-precision latent copy
     const uint16_t* w;        // packed weights (forward and backward blocks)
     const float* bias;        // packed biases
-    int l0, l1, shift0, shift1, tex_w, hidden;
+    int l0, hidden;
     const int2* xy;
     const float4* target;
     int n;                    // samples
     float gscale;             // 2 / (4 n)
-    float* glat;              // latent gradient (flat, atomics), may be null
+    int64_t* glat;            // latent gradient, fixed point (flat, atomics), may be null
     float* partials;          // [waves][mlp_count]
     float* loss_part;         // [waves]
     int mlp_count;
@@ -278,8 +297,9 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
         const int b = tile * 16 + j;
         const bool valid = b < a.n;
         const int2 p = valid ? a.xy[b] : make_int2(0, 0);
-        LatentTap tap;
-        f4 X = latent_features<P>(a.lat0, a.lat1, a.l0, a.l1, a.shift0, a.shift1, a.tex_w, p.x, p.y, g, tap);
+        LatentFetch tap;
+        latent_fetch(a.grid, p.x, p.y, g, tap);
+        f4 X = latent_combine<P>(tap);
         if (!valid) X = zero;
         f4 z1[4], z2[4];
         const f4 y = mlp_forward<P>(W, B, X, z1, z2);
@@ -326,12 +346,15 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
         f4 dx = Mfma<P>::k32(w1a[0], dz1b[0], zero);
         dx = Mfma<P>::k32(w1a[1], dz1b[1], dx);
         if (a.glat && valid) {
-            float* gl = a.glat + (g >= 2 ? (int64_t)a.l0 * a.l0 * 8 : 0) + 4 * (g & 1);
+            int64_t* gl = a.glat + (g >= 2 ? (int64_t)a.l0 * a.l0 * 8 : 0) + 4 * (g & 1);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    unsafeAtomicAdd(gl + (int64_t)tap.cell[q] * 8 + i, tap.w[q] * dx[i]);
+                for (int i = 0; i < 4; ++i) {
+                    const long long v = __float2ll_rn(tap.w[q] * dx[i] * kFxScale);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(gl + (int64_t)tap.cell[q] * 8 + i),
+                              (unsigned long long)v);
+                }
         }
 
         // weight gradients: batch contractions on MFMA over the 16 samples
@@ -476,7 +499,8 @@ struct AdamArgs {
     float* master;
     float* m;
     float* v;
-    const float* grad;
+    const float* grad;        // MLP part (p >= mlp0)
+    const int64_t* glat_fx;   // latent part, fixed point
     int64_t total, mlp0;
     int hidden;
     float lr, b1, b2, eps, bc1, bc2;  // bias corrections 1 - beta^t
@@ -492,7 +516,7 @@ __global__ void k_adam(AdamArgs a)
     if (p >= a.total) return;
     float th = a.master[p];
     if (UPDATE) {
-        const float gr = a.grad[p];
+        const float gr = p < a.mlp0 ? (float)a.glat_fx[p] * kFxInv : a.grad[p];
         const float m = __builtin_fmaf(a.b1, a.m[p], (1.f - a.b1) * gr);
         const float v = __builtin_fmaf(a.b2, a.v[p], (1.f - a.b2) * gr * gr);
         a.m[p] = m;
@@ -545,6 +569,19 @@ struct DeviceScope {
     }
 };
 
+LatentGrid latent_grid(const ctf_decoder_desc& d, const uint16_t* base)
+{
+    LatentGrid G;
+    G.base = base;
+    G.lvl1 = (uint32_t)((size_t)d.l0 * d.l0 * 16);
+    G.log_l0 = ilog2(d.l0);
+    G.log_l1 = ilog2(d.l1);
+    G.shift0 = ilog2(d.tex_w / d.l0);
+    G.shift1 = ilog2(d.tex_w / d.l1);
+    G.tex_w = d.tex_w;
+    return G;
+}
+
 int train_waves(int n)
 {
     const int tiles = (n + 15) / 16;
@@ -583,6 +620,7 @@ hipError_t launch_adam(ctf_decoder d, float lr, hipStream_t s)
     a.m = d->m;
     a.v = d->v;
     a.grad = d->grad;
+    a.glat_fx = d->glat_fx;
     a.total = d->lay.total;
     a.mlp0 = d->lay.mlp0;
     a.hidden = d->desc.hidden;
@@ -613,29 +651,27 @@ hipError_t ensure_lp(ctf_decoder d, int precision, hipStream_t s)
     return e;
 }
 
+// Loss and gradient of a batch: the MLP part lands in grad[mlp0..]; the
+// latent part in d->glat_fx (fixed point), copied to grad[0..mlp0) as float
+// when latent_to_grad is set (training reads the fixed-point sums directly).
 template <int P>
 hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target, int32_t n,
-                          float* loss, float* grad, hipStream_t s)
+                          float* loss, float* grad, bool latent_to_grad, hipStream_t s)
 {
     const Layout& L = d->lay;
     const int fb = 1024;
-    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, s, grad, L.mlp0, 0.f);
+    hipLaunchKernelGGL(k_zero64, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0);
     TrainArgs a;
-    a.lat0 = d->lat_lp;
-    a.lat1 = d->lat_lp + L.lat1;
+    a.grid = latent_grid(d->desc, d->lat_lp);
     a.w = d->w_lp;
     a.bias = d->bias_c;
     a.l0 = d->desc.l0;
-    a.l1 = d->desc.l1;
-    a.shift0 = ilog2(d->desc.tex_w / d->desc.l0);
-    a.shift1 = ilog2(d->desc.tex_w / d->desc.l1);
-    a.tex_w = d->desc.tex_w;
     a.hidden = d->desc.hidden;
     a.xy = reinterpret_cast<const int2*>(xy);
     a.target = reinterpret_cast<const float4*>(target);
     a.n = n;
     a.gscale = 2.0f / (4.0f * (float)n);
-    a.glat = grad;
+    a.glat = d->glat_fx;
     a.partials = d->partials;
     a.loss_part = d->loss_part;
     a.mlp_count = (int)L.mlp_count;
@@ -648,6 +684,7 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
                        (int)L.mlp_count, d->slices);
     hipLaunchKernelGGL(k_reduce2, dim3(gx), dim3(rb), 0, s, d->slices, nsl, (int)L.mlp_count,
                        grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
+    if (latent_to_grad) hipLaunchKernelGGL(k_fx_to_float, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0, grad);
     return hipGetLastError();
 }
 
@@ -665,7 +702,7 @@ ctf_status ctf_decoder_destroy(ctf_decoder d)
 {
     if (!d) return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_destroy: NULL decoder");
     DeviceScope ds(d->ctx->device);
-    for (void* p : {(void*)d->master, (void*)d->m, (void*)d->v, (void*)d->grad, (void*)d->lat_lp,
+    for (void* p : {(void*)d->master, (void*)d->m, (void*)d->v, (void*)d->grad, (void*)d->glat_fx, (void*)d->lat_lp,
                     (void*)d->w_lp, (void*)d->bias_c, (void*)d->xy, (void*)d->target,
                     (void*)d->partials, (void*)d->loss_part, (void*)d->slices, (void*)d->loss_tmp})
         if (p) (void)hipFree(p);
@@ -699,6 +736,7 @@ ctf_status ctf_decoder_create(ctf_context ctx, const ctf_decoder_desc* desc, con
     if (e == hipSuccess) e = hipMalloc(&dec->m, bytes);
     if (e == hipSuccess) e = hipMalloc(&dec->v, bytes);
     if (e == hipSuccess) e = hipMalloc(&dec->grad, bytes);
+    if (e == hipSuccess) e = hipMalloc(&dec->glat_fx, (size_t)dec->lay.mlp0 * 8);
     if (e == hipSuccess) e = hipMalloc(&dec->lat_lp, (size_t)dec->lay.mlp0 * 2);
     if (e == hipSuccess) e = hipMalloc(&dec->w_lp, kAllElems * 2);
     if (e == hipSuccess) e = hipMalloc(&dec->bias_c, kBiasFloats * 4);
@@ -794,8 +832,8 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder d, const int32_t* xy, const float* 
     hipError_t e = ensure_batch(d, n);
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
     if (e == hipSuccess)
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, s)
-                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, s);
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, s)
+                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, s);
     return e == hipSuccess ? CTF_OK : hip_fail(e, "ctf_decoder_loss_grad");
 }
 
@@ -836,8 +874,8 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
             hipLaunchKernelGGL(k_sample<CTF_TEX_TABLE>, sg, dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy, tg);
         }
         float* lt = loss_trace ? loss_trace + it : d->loss_tmp;
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, s)
-                                  : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, s);
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, false, s)
+                                  : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, false, s);
         if (e != hipSuccess) break;
         d->step += 1;
         e = precision == CTF_BF16 ? launch_adam<CTF_BF16, true>(d, lr, s) : launch_adam<CTF_FP16, true>(d, lr, s);
@@ -877,17 +915,9 @@ ctf_status ctf_internal_decoder_texture(ctf_texture t)
     }
     t->dec_buf = buf;
     DevDecoderWeights& W = t->dec;
-    W.l0 = d->desc.l0;
-    W.l1 = d->desc.l1;
-    W.tex_w = d->desc.tex_w;
-    W.shift0 = ilog2(d->desc.tex_w / d->desc.l0);
-    W.shift1 = ilog2(d->desc.tex_w / d->desc.l1);
+    W.grid = latent_grid(d->desc, reinterpret_cast<const uint16_t*>(buf));
     W.precision = prec;
-    W.lat0 = reinterpret_cast<const uint16_t*>(buf);
-    W.lat1 = W.lat0 + d->lay.lat1;
-    W.w1 = reinterpret_cast<const uint16_t*>(buf + o_w);
-    W.w2 = W.w1;
-    W.w3 = W.w1;
+    W.w = reinterpret_cast<const uint16_t*>(buf + o_w);
     W.bias = reinterpret_cast<const float*>(buf + o_b);
     return CTF_OK;
 }

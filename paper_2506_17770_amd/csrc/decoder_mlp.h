@@ -140,77 +140,135 @@ struct Biases {
     }
 };
 
+// Two floats -> one 32-bit word of two 16-bit values, round to nearest even
+// (one v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32: written as a vector conversion
+// so the backend keeps the packed form).
+template <int P>
+__device__ __forceinline__ uint32_t cvt2(float a, float b);
+
+template <>
+__device__ __forceinline__ uint32_t cvt2<CTF_FP16>(float a, float b)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2));
+}
+
+template <>
+__device__ __forceinline__ uint32_t cvt2<CTF_BF16>(float a, float b)
+{
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2));
+}
+
+// ReLU on two packed 16-bit floats: both formats keep the sign in the top
+// bit, so a signed 16-bit max against 0 clears negative values (one
+// v_pk_max_i16, no NaN canonicalisation of the MFMA results).
+__device__ __forceinline__ uint32_t relu2(uint32_t w)
+{
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const s2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s2, w), z));
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // ReLU and conversion of two C blocks into one K=32 B operand (pi order).
 template <int P>
 __device__ __forceinline__ u16x8 relu_pack(f4 lo, f4 hi)
 {
-    u16x8 r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = Mfma<P>::cvt(lo[i] > 0.f ? lo[i] : 0.f);
-        r[4 + i] = Mfma<P>::cvt(hi[i] > 0.f ? hi[i] : 0.f);
-    }
-    return r;
+    u32x4 r;
+    r[0] = relu2(cvt2<P>(lo[0], lo[1]));
+    r[1] = relu2(cvt2<P>(lo[2], lo[3]));
+    r[2] = relu2(cvt2<P>(hi[0], hi[1]));
+    r[3] = relu2(cvt2<P>(hi[2], hi[3]));
+    return __builtin_bit_cast(u16x8, r);
 }
 
 template <int P>
 __device__ __forceinline__ u16x8 pack8(f4 lo, f4 hi)
 {
-    u16x8 r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = Mfma<P>::cvt(lo[i]);
-        r[4 + i] = Mfma<P>::cvt(hi[i]);
-    }
-    return r;
+    u32x4 r;
+    r[0] = cvt2<P>(lo[0], lo[1]);
+    r[1] = cvt2<P>(lo[2], lo[3]);
+    r[2] = cvt2<P>(hi[0], hi[1]);
+    r[3] = cvt2<P>(hi[2], hi[3]);
+    return __builtin_bit_cast(u16x8, r);
 }
 
-// Latent features of texel (x, y) for this lane: level g/2, channels
-// 4 (g%2) .. +3.  Sample point (x + 1/2) L / W - 1/2 (exact in float32 for
-// the wrapped coordinate), bilinear with repeat addressing.  Returns the 4
-// features and the corner cells / weights (for the gradient scatter).
-struct LatentTap {
-    int cell[4];
-    float w[4];
+template <int P>
+__device__ __forceinline__ u16x4 pack4(f4 x)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 r;
+    r[0] = cvt2<P>(x[0], x[1]);
+    r[1] = cvt2<P>(x[2], x[3]);
+    return __builtin_bit_cast(u16x4, r);
+}
+
+// Latent grids of one decoder: both levels in one allocation (level 1 at
+// byte offset lvl1), cells of 8 16-bit channels (16 bytes), side 2^log_l.
+struct LatentGrid {
+    const uint16_t* __restrict__ base;
+    uint32_t lvl1;          // byte offset of level 1
+    int log_l0, log_l1;     // log2 of the sides
+    int shift0, shift1;     // log2(tex_w / side)
+    int tex_w;
 };
 
-template <int P>
-__device__ __forceinline__ f4 latent_features(const uint16_t* __restrict__ lat0,
-                                              const uint16_t* __restrict__ lat1, int l0, int l1,
-                                              int shift0, int shift1, int tex_w, int x, int y,
-                                              int g, LatentTap& tap)
+// Latent taps of texel (x, y) for this lane (level g/2, channels 4 (g%2)..+3):
+// sample point (x + 1/2) L / W - 1/2 for the wrapped coordinate (exact in
+// float32), four corners with repeat addressing and their bilinear weights.
+// latent_fetch issues the four 8-byte loads; latent_combine interpolates.
+struct LatentFetch {
+    u16x4 v[4];
+    float w[4];
+    uint32_t cell[4];
+};
+
+__device__ __forceinline__ void latent_fetch(const LatentGrid& G, int x, int y, int g, LatentFetch& F)
 {
     const int level = g >> 1;
-    const int L = level ? l1 : l0;
-    const int shift = level ? shift1 : shift0;
-    const uint16_t* __restrict__ lat = level ? lat1 : lat0;
-    const int xw = x & (tex_w - 1), yw = y & (tex_w - 1);
+    const int logL = level ? G.log_l1 : G.log_l0;
+    const int shift = level ? G.shift1 : G.shift0;
+    const int m = (1 << logL) - 1;
+    const int xw = x & (G.tex_w - 1), yw = y & (G.tex_w - 1);
     const float inv = __builtin_ldexpf(1.0f, -shift);
     const float off = __builtin_fmaf(0.5f, inv, -0.5f);
     const float gx = __builtin_fmaf((float)xw, inv, off);
     const float gy = __builtin_fmaf((float)yw, inv, off);
     const float cx = __builtin_floorf(gx), cy = __builtin_floorf(gy);
     const float fx = gx - cx, fy = gy - cy;
-    const int m = L - 1;
-    const int x0 = ((int)cx + L) & m, x1 = ((int)cx + 1) & m;
-    const int y0 = ((int)cy + L) & m, y1 = ((int)cy + 1) & m;
-    tap.cell[0] = y0 * L + x0;
-    tap.cell[1] = y0 * L + x1;
-    tap.cell[2] = y1 * L + x0;
-    tap.cell[3] = y1 * L + x1;
+    const int icx = (int)cx, icy = (int)cy;
+    const uint32_t x0 = (uint32_t)(icx & m), x1 = (uint32_t)((icx + 1) & m);
+    const uint32_t y0 = (uint32_t)(icy & m) << logL, y1 = (uint32_t)((icy + 1) & m) << logL;
+    F.cell[0] = y0 | x0;
+    F.cell[1] = y0 | x1;
+    F.cell[2] = y1 | x0;
+    F.cell[3] = y1 | x1;
     const float ifx = 1.0f - fx, ify = 1.0f - fy;
-    tap.w[0] = ifx * ify;
-    tap.w[1] = fx * ify;
-    tap.w[2] = ifx * fy;
-    tap.w[3] = fx * fy;
-    const int ch0 = 4 * (g & 1);
+    F.w[0] = ifx * ify;
+    F.w[1] = fx * ify;
+    F.w[2] = ifx * fy;
+    F.w[3] = fx * fy;
+    const uint32_t byte0 = (level ? G.lvl1 : 0u) + 8u * (uint32_t)(g & 1);
+    const char* __restrict__ b = reinterpret_cast<const char*>(G.base);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        F.v[q] = *reinterpret_cast<const u16x4*>(b + (byte0 + (F.cell[q] << 4)));
+}
+
+template <int P>
+__device__ __forceinline__ f4 latent_combine(const LatentFetch& F)
+{
     f4 r = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const u16x4 v = *reinterpret_cast<const u16x4*>(lat + (size_t)tap.cell[q] * 8 + ch0);
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) r[i] = __builtin_fmaf(tap.w[q], Mfma<P>::load(v[i]), r[i]);
-    }
+        for (int i = 0; i < 4; ++i) r[i] = __builtin_fmaf(F.w[q], Mfma<P>::load(F.v[q][i]), r[i]);
     return r;
 }
 
@@ -221,9 +279,7 @@ template <int P>
 __device__ __forceinline__ f4 mlp_forward(const FwdWeights<P>& W, const Biases& B, f4 X, f4* z1,
                                           f4* z2)
 {
-    u16x4 xb;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) xb[i] = Mfma<P>::cvt(X[i]);
+    const u16x4 xb = pack4<P>(X);
     f4 d1[4];
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb) d1[hb] = Mfma<P>::k16(W.w1[hb], xb, B.b1[hb]);

@@ -30,13 +30,6 @@ struct DecLds {
     uint8_t bytes[256];
 };
 
-struct DecArgs {
-    const uint16_t* lat0;
-    const uint16_t* lat1;
-    const uint16_t* w;
-    const float* bias;
-    int l0, l1, shift0, shift1, tex_w;
-};
 
 __device__ int dec_list_sorted(DecLds& L, bool inA, const Footprint& f, int xmin, int ymin)
 {
@@ -96,254 +89,375 @@ __device__ __forceinline__ int dec_list_find(const DecLds& L, int n, uint64_t ke
     return lo;
 }
 
+template <int P>
+__device__ __forceinline__ void fetch_row(const int2* rows, int R, int row, const LatentGrid& G, int g,
+                                          LatentFetch& F)
+{
+    const int2 p = row < R ? rows[row] : make_int2(0, 0);
+    latent_fetch(G, p.x, p.y, g, F);
+}
+
+template <int P>
+__device__ __forceinline__ void finish_row(float4* vals, int R, int row, const FwdWeights<P>& W,
+                                           const Biases& Bz, const LatentFetch& F, int g)
+{
+    const f4 y = mlp_forward<P>(W, Bz, latent_combine<P>(F), nullptr, nullptr);
+    if (g == 0 && row < R) vals[row] = make_float4(y[0], y[1], y[2], y[3]);
+}
+
+// rows[0..R) -> vals[0..R) in 16-row tiles, two fetch buffers in ping-pong.
+// Every prefetch is issued unconditionally (rows past R fetch cell 0), so
+// each path reaches the next tile's MLP with the same loads outstanding and
+// the wait before it covers only the current tile's gathers.
+template <int P>
+__device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& G, const FwdWeights<P>& W,
+                                            const Biases& Bz, int j, int g)
+{
+    const int T = (R + 15) >> 4;
+    if (T == 0) return;
+    LatentFetch fa, fb;
+    fetch_row<P>(L.rows, R, j, G, g, fa);
+    for (int t = 0; t < T; t += 2) {
+        fetch_row<P>(L.rows, R, 16 * (t + 1) + j, G, g, fb);
+        finish_row<P>(L.vals, R, 16 * t + j, W, Bz, fa, g);
+        if (t + 1 >= T) break;
+        fetch_row<P>(L.rows, R, 16 * (t + 2) + j, G, g, fa);
+        finish_row<P>(L.vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
+    }
+}
+
+// One tile of the decoder-path filter: decisions, row list, MFMA decode,
+// gather and outputs.  `f` is the lanes' footprint (already in this
+// layer's coordinates); a.out / a.tile_stats / a.stf_xy point at this
+// layer's planes.
 template <int METHOD, int P, bool STATS>
-__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, DecArgs D)
+__device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& G, const FwdWeights<P>& W,
+                                         const Biases& Bz, DecLds& L, int64_t tile, const Footprint& f,
+                                         FrameCounters& fc)
+{
+    const int lane = lane_id();
+    const int j = lane & 15, g = lane >> 4;
+    const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    const bool in_screen = px < a.sw && py < a.sh;
+    const int64_t pix = (int64_t)py * a.sw + px;
+    const bool inA = f.active && f.magnify;
+    const uint64_t act = ballot(f.active);
+    const uint64_t A = ballot(inA);
+    const int nA = popc64(A);
+
+    int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
+    constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    if ((kCollab || STATS) && nA > 0) {
+        xmin = wave_min(inA ? f.x0 : INT32_MAX);
+        ymin = wave_min(inA ? f.y0 : INT32_MAX);
+        bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
+        bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
+    }
+    const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+
+    uint64_t B[4] = {0, 0, 0, 0};
+    int nmask = 0;
+    constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
+    if (kNeedMask && fits16) {
+        reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
+        wave_lds_sync();
+        if (inA) {
+            const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
+            L.bytes[t] = 1;
+            L.bytes[t + 1] = 1;
+            L.bytes[t + 16] = 1;
+            L.bytes[t + 17] = 1;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) B[w] = ballot(L.bytes[64 * w + lane] != 0);
+        int base = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if ((B[w] >> lane) & 1u) {
+                const int r = base + mbcnt(B[w]);
+                L.items[r] = (uint16_t)(64 * w + lane);
+                L.rank[64 * w + lane] = (uint8_t)r;
+            }
+            base += popc64(B[w]);
+        }
+        nmask = base;
+        wave_lds_sync();
+    }
+
+    const int k = a.max_evals;
+    int n = 0;
+    bool cap_ok = true, count_ok = true, success = false, sorted = false;
+    int unique = nmask;
+    if constexpr (METHOD == CTF_BOX) {
+        const int64_t area = (int64_t)bbw * bbh;
+        n = area > INT32_MAX ? INT32_MAX : (int)area;
+        cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
+        count_ok = area <= (int64_t)k * nA;
+        success = nA > 0 && cap_ok && count_ok;
+    } else if constexpr (METHOD == CTF_MASK) {
+        cap_ok = fits16;
+        n = fits16 ? nmask : 0;
+        count_ok = n <= k * nA;
+        success = fits16 && count_ok;
+    } else if constexpr (METHOD == CTF_LIST) {
+        if (nA > 0 && !fits16) {
+            n = dec_list_sorted(L, inA, f, xmin, ymin);
+            sorted = true;
+        } else {
+            n = nmask;
+        }
+        unique = n;
+        count_ok = n <= k * nA;
+        success = nA > 0 && count_ok;
+    }
+    if constexpr (STATS && METHOD != CTF_LIST) {
+        if (nA > 0 && !fits16) unique = dec_list_sorted(L, inA, f, xmin, ymin);
+    }
+    if (nA == 0) unique = 0;
+
+    bool exact, draws;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        exact = f.active;
+        draws = false;
+    } else if constexpr (METHOD == CTF_STF1) {
+        exact = false;
+        draws = f.active;
+    } else {
+        exact = inA && success;
+        draws = f.active && !exact;
+    }
+    const uint64_t stfmask = ballot(draws);
+    const int nstf = popc64(stfmask);
+    int2 pick = make_int2(INT32_MIN, INT32_MIN);
+    if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
+
+    // ---- row list: the texels to produce
+    const int rank_act = mbcnt(act);
+    const int ns = success ? n : 0;
+    int R;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        R = 4 * popc64(act);
+        if (f.active) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
+        }
+    } else {
+        R = ns + nstf;
+        for (int i = lane; i < ns; i += kWave) {
+            int ex, ey;
+            if constexpr (METHOD == CTF_BOX) {
+                ex = xmin + i % bbw;
+                ey = ymin + i / bbw;
+            } else {
+                if (sorted) {
+                    const uint64_t key = L.keys[i];
+                    ex = xmin + (int)(uint32_t)key;
+                    ey = ymin + (int)(key >> 32);
+                } else {
+                    const int t = L.items[i];
+                    ex = xmin + (t & 15);
+                    ey = ymin + (t >> 4);
+                }
+            }
+            L.rows[i] = make_int2(ex, ey);
+            if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+        }
+        if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
+    }
+    wave_lds_sync();
+
+    // ---- decode the rows, 16 per MFMA tile; the latent gathers of the
+    // next tile are in flight during the MLP of the current one
+    decode_rows<P>(L, R, G, W, Bz, j, g);
+    wave_lds_sync();
+
+    // ---- gather and weight
+    float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        if (exact) {
+            const int b = 4 * rank_act;
+            res = bilerp(f.s, f.t, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
+        }
+    } else {
+        if (draws) res = L.vals[ns + mbcnt(stfmask)];
+        if constexpr (kCollab) {
+            if (exact) {
+                int idx[4];
+                if constexpr (METHOD == CTF_BOX) {
+                    const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
+                    idx[0] = b;
+                    idx[1] = b + 1;
+                    idx[2] = b + bbw;
+                    idx[3] = b + bbw + 1;
+                } else if (sorted) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
+                                             (uint32_t)(f.x0 + (q & 1) - xmin);
+                        idx[q] = dec_list_find(L, n, key);
+                    }
+                } else {
+                    const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
+                    idx[0] = L.rank[t];
+                    idx[1] = L.rank[t + 1];
+                    idx[2] = L.rank[t + 16];
+                    idx[3] = L.rank[t + 17];
+                }
+                res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
+            }
+        }
+    }
+    if (in_screen) {
+        reinterpret_cast<float4*>(a.out)[pix] = res;
+        if (a.stf_xy)
+            reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+    }
+    if (lane == 0) {
+        if (a.tile_stats) {
+            ctf_tile_stats S;
+            S.active = act;
+            S.part = A;
+            S.stf = stfmask;
+            for (int w = 0; w < 4; ++w) S.mask[w] = fits16 ? B[w] : 0ull;
+            S.xmin = xmin;
+            S.ymin = ymin;
+            S.bbw = bbw;
+            S.bbh = bbh;
+            S.n = n;
+            S.unique = unique;
+            S.evals = R;
+            S.flags = (success ? CTF_TILE_OK : 0) | (nA && !cap_ok ? CTF_TILE_CAP : 0) |
+                      (nA && cap_ok && !count_ok ? CTF_TILE_OVERFLOW : 0) | (nA == 0 ? CTF_TILE_EMPTY : 0);
+            for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
+            a.tile_stats[tile] = S;
+        }
+    }
+    if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), (R + 15) & ~15, kCollab && success,
+                    kCollab && nA && !success);
+    wave_lds_sync();  // the next tile reuses this wave's LDS slice
+}
+
+// Inputs of a tile for this lane, NaN (inactive) outside the band or screen.
+__device__ __forceinline__ void load_tile_px(const FilterArgs& a, int64_t t, int64_t band_e, float2& uv, float4& d)
+{
+    const int lane = lane_id();
+    uv = make_float2(__builtin_nanf(""), 0.f);
+    d = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t >= band_e) return;
+    const int px = (int)(t % a.tiles_x) * kTile + (lane & 7), py = (int)(t / a.tiles_x) * kTile + (lane >> 3);
+    if (px < a.sw && py < a.sh) {
+        const int64_t q = (int64_t)py * a.sw + px;
+        uv = reinterpret_cast<const float2*>(a.uv)[q];
+        d = reinterpret_cast<const float4*>(a.duv)[q];
+    }
+}
+
+// XCD-aware band of tiles for this wave: workgroups go round-robin over the
+// 8 XCDs, so band b of the screen is walked by the workgroups of XCD b.
+struct Band {
+    int64_t begin, end;
+    int lw, nw;
+    __device__ Band(int64_t ntiles, int wid)
+    {
+        const int xcd = blockIdx.x & 7;
+        lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
+        nw = (int)(gridDim.x >> 3) * kDecWaves;
+        begin = ntiles * xcd / 8;
+        end = ntiles * (xcd + 1) / 8;
+    }
+};
+
+template <int METHOD, int P, bool STATS>
+__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, DevDecoderWeights D)
 {
     __shared__ DecLds lds_all[kDecWaves];
     const int wid = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int j = lane & 15, g = lane >> 4;
     DecLds& L = lds_all[wid];
-
     FwdWeights<P> W;
     W.load(D.w, lane);
     Biases Bz;
     Bz.load(D.bias, lane);
-
-    // XCD-aware band of tiles for this wave
-    const int xcd = blockIdx.x & 7;
-    const int nblk_x = (int)(gridDim.x >> 3);
-    const int lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
-    const int nw = nblk_x * kDecWaves;
-    const int64_t band_b = a.ntiles * xcd / 8, band_e = a.ntiles * (xcd + 1) / 8;
+    const float tex_w = (float)D.grid.tex_w;
+    const Band band(a.ntiles, wid);
     FrameCounters fc;
 
-    for (int64_t tile = band_b + lw; tile < band_e; tile += nw) {
-        const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
-        const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-        const bool in_screen = px < a.sw && py < a.sh;
-        const int64_t pix = (int64_t)py * a.sw + px;
-        Footprint f;
-        {
-            float2 uv = make_float2(__builtin_nanf(""), 0.f);
-            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (in_screen) {
-                uv = reinterpret_cast<const float2*>(a.uv)[pix];
-                d = reinterpret_cast<const float4*>(a.duv)[pix];
-            }
-            f = footprint(uv.x, uv.y, d, (float)D.tex_w, (float)D.tex_w);
-        }
-        const bool inA = f.active && f.magnify;
-        const uint64_t act = ballot(f.active);
-        const uint64_t A = ballot(inA);
-        const int nA = popc64(A);
-
-        int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
-        constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
-        if ((kCollab || STATS) && nA > 0) {
-            xmin = wave_min(inA ? f.x0 : INT32_MAX);
-            ymin = wave_min(inA ? f.y0 : INT32_MAX);
-            bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
-            bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
-        }
-        const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
-
-        uint64_t B[4] = {0, 0, 0, 0};
-        int nmask = 0;
-        constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
-        if (kNeedMask && fits16) {
-            reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
-            wave_lds_sync();
-            if (inA) {
-                const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                L.bytes[t] = 1;
-                L.bytes[t + 1] = 1;
-                L.bytes[t + 16] = 1;
-                L.bytes[t + 17] = 1;
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int w = 0; w < 4; ++w) B[w] = ballot(L.bytes[64 * w + lane] != 0);
-            int base = 0;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                if ((B[w] >> lane) & 1u) {
-                    const int r = base + mbcnt(B[w]);
-                    L.items[r] = (uint16_t)(64 * w + lane);
-                    L.rank[64 * w + lane] = (uint8_t)r;
-                }
-                base += popc64(B[w]);
-            }
-            nmask = base;
-            wave_lds_sync();
-        }
-
-        const int k = a.max_evals;
-        int n = 0;
-        bool cap_ok = true, count_ok = true, success = false, sorted = false;
-        int unique = nmask;
-        if constexpr (METHOD == CTF_BOX) {
-            const int64_t area = (int64_t)bbw * bbh;
-            n = area > INT32_MAX ? INT32_MAX : (int)area;
-            cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
-            count_ok = area <= (int64_t)k * nA;
-            success = nA > 0 && cap_ok && count_ok;
-        } else if constexpr (METHOD == CTF_MASK) {
-            cap_ok = fits16;
-            n = fits16 ? nmask : 0;
-            count_ok = n <= k * nA;
-            success = fits16 && count_ok;
-        } else if constexpr (METHOD == CTF_LIST) {
-            if (nA > 0 && !fits16) {
-                n = dec_list_sorted(L, inA, f, xmin, ymin);
-                sorted = true;
-            } else {
-                n = nmask;
-            }
-            unique = n;
-            count_ok = n <= k * nA;
-            success = nA > 0 && count_ok;
-        }
-        if constexpr (STATS && METHOD != CTF_LIST) {
-            if (nA > 0 && !fits16) unique = dec_list_sorted(L, inA, f, xmin, ymin);
-        }
-        if (nA == 0) unique = 0;
-
-        bool exact, draws;
-        if constexpr (METHOD == CTF_BILINEAR4) {
-            exact = f.active;
-            draws = false;
-        } else if constexpr (METHOD == CTF_STF1) {
-            exact = false;
-            draws = f.active;
-        } else {
-            exact = inA && success;
-            draws = f.active && !exact;
-        }
-        const uint64_t stfmask = ballot(draws);
-        const int nstf = popc64(stfmask);
-        int2 pick = make_int2(INT32_MIN, INT32_MIN);
-        if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
-
-        // ---- row list: the texels to produce
-        const int rank_act = mbcnt(act);
-        const int ns = success ? n : 0;
-        int R;
-        if constexpr (METHOD == CTF_BILINEAR4) {
-            R = 4 * popc64(act);
-            if (f.active) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
-            }
-        } else {
-            R = ns + nstf;
-            for (int i = lane; i < ns; i += kWave) {
-                int ex, ey;
-                if constexpr (METHOD == CTF_BOX) {
-                    ex = xmin + i % bbw;
-                    ey = ymin + i / bbw;
-                } else {
-                    if (sorted) {
-                        const uint64_t key = L.keys[i];
-                        ex = xmin + (int)(uint32_t)key;
-                        ey = ymin + (int)(key >> 32);
-                    } else {
-                        const int t = L.items[i];
-                        ex = xmin + (t & 15);
-                        ey = ymin + (t >> 4);
-                    }
-                }
-                L.rows[i] = make_int2(ex, ey);
-                if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
-            }
-            if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
-        }
-        wave_lds_sync();
-
-        // ---- decode the rows, 16 per MFMA tile
-        for (int r0 = 0; r0 < R; r0 += 16) {
-            const int row = r0 + j;
-            const bool valid = row < R;
-            const int2 p = valid ? L.rows[row] : make_int2(0, 0);
-            LatentTap tap;
-            const f4 X = latent_features<P>(D.lat0, D.lat1, D.l0, D.l1, D.shift0, D.shift1, D.tex_w, p.x, p.y, g, tap);
-            const f4 y = mlp_forward<P>(W, Bz, X, nullptr, nullptr);
-            if (g == 0 && valid) L.vals[row] = make_float4(y[0], y[1], y[2], y[3]);
-        }
-        wave_lds_sync();
-
-        // ---- gather and weight
-        float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (METHOD == CTF_BILINEAR4) {
-            if (exact) {
-                const int b = 4 * rank_act;
-                res = bilerp(f.s, f.t, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
-            }
-        } else {
-            if (draws) res = L.vals[ns + mbcnt(stfmask)];
-            if constexpr (kCollab) {
-                if (exact) {
-                    int idx[4];
-                    if constexpr (METHOD == CTF_BOX) {
-                        const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
-                        idx[0] = b;
-                        idx[1] = b + 1;
-                        idx[2] = b + bbw;
-                        idx[3] = b + bbw + 1;
-                    } else if (sorted) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                                 (uint32_t)(f.x0 + (q & 1) - xmin);
-                            idx[q] = dec_list_find(L, n, key);
-                        }
-                    } else {
-                        const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                        idx[0] = L.rank[t];
-                        idx[1] = L.rank[t + 1];
-                        idx[2] = L.rank[t + 16];
-                        idx[3] = L.rank[t + 17];
-                    }
-                    res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
-                }
-            }
-        }
-        if (in_screen) {
-            reinterpret_cast<float4*>(a.out)[pix] = res;
-            if (a.stf_xy)
-                reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
-        }
-        if (lane == 0) {
-            if (a.tile_stats) {
-                ctf_tile_stats S;
-                S.active = act;
-                S.part = A;
-                S.stf = stfmask;
-                for (int w = 0; w < 4; ++w) S.mask[w] = fits16 ? B[w] : 0ull;
-                S.xmin = xmin;
-                S.ymin = ymin;
-                S.bbw = bbw;
-                S.bbh = bbh;
-                S.n = n;
-                S.unique = unique;
-                S.evals = R;
-                S.flags = (success ? CTF_TILE_OK : 0) | (nA && !cap_ok ? CTF_TILE_CAP : 0) |
-                          (nA && cap_ok && !count_ok ? CTF_TILE_OVERFLOW : 0) | (nA == 0 ? CTF_TILE_EMPTY : 0);
-                for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
-                a.tile_stats[tile] = S;
-            }
-        }
-        if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), (R + 15) & ~15, kCollab && success,
-                        kCollab && nA && !success);
-        wave_lds_sync();  // the next tile reuses this wave's LDS slice
+    // the inputs of the wave's next tile are loaded one tile ahead
+    float2 uv_next;
+    float4 d_next;
+    load_tile_px(a, band.begin + band.lw, band.end, uv_next, d_next);
+    for (int64_t tile = band.begin + band.lw; tile < band.end; tile += band.nw) {
+        const float2 uv = uv_next;
+        const float4 d = d_next;
+        load_tile_px(a, tile + band.nw, band.end, uv_next, d_next);
+        const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
+        dec_tile<METHOD, P, STATS>(a, D.grid, W, Bz, L, tile, f, fc);
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
 
-// rgba[i] = decoder(xy[i]): 16 texels per MFMA tile, persistent waves.
+// Several material layers in one launch: layer l samples its own decoder at
+// uv_l = M_l uv (derivatives alike).  Layers are the outer loop so that one
+// layer's latent grids stay resident in the L2 while its tiles are walked;
+// each wave reloads the MLP weights once per layer.
+constexpr int kMaxLayers = 8;
+
+struct LayerSet {
+    DevDecoderWeights dec[kMaxLayers];
+    float xf[kMaxLayers][4];   // row-major 2x2
+    int n;
+};
+
+template <int METHOD, int P, bool STATS>
+__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_layers(FilterArgs a, LayerSet LS)
+{
+    __shared__ DecLds lds_all[kDecWaves];
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    DecLds& L = lds_all[wid];
+    const Band band(a.ntiles, wid);
+    const int64_t npix = (int64_t)a.sw * a.sh;
+    FrameCounters fc;
+    for (int l = 0; l < LS.n; ++l) {
+        const DevDecoderWeights& D = LS.dec[l];
+        FwdWeights<P> W;
+        W.load(D.w, lane);
+        Biases Bz;
+        Bz.load(D.bias, lane);
+        const float tex_w = (float)D.grid.tex_w;
+        const float m00 = LS.xf[l][0], m01 = LS.xf[l][1], m10 = LS.xf[l][2], m11 = LS.xf[l][3];
+        FilterArgs al = a;
+        al.out = a.out + (size_t)l * npix * 4;
+        al.tile_stats = a.tile_stats ? a.tile_stats + (size_t)l * a.ntiles : nullptr;
+        al.stf_xy = a.stf_xy ? a.stf_xy + (size_t)l * npix * 2 : nullptr;
+        al.lists = nullptr;
+        al.layer = (uint32_t)l;
+        float2 uv_next;
+        float4 d_next;
+        load_tile_px(a, band.begin + band.lw, band.end, uv_next, d_next);
+        for (int64_t tile = band.begin + band.lw; tile < band.end; tile += band.nw) {
+            const float2 uv = uv_next;
+            const float4 d = d_next;
+            load_tile_px(a, tile + band.nw, band.end, uv_next, d_next);
+            // layer coordinates, float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u)
+            const float lu = __builtin_fmaf(m01, uv.y, m00 * uv.x), lv = __builtin_fmaf(m11, uv.y, m10 * uv.x);
+            const float4 ld = make_float4(__builtin_fmaf(m01, d.y, m00 * d.x), __builtin_fmaf(m11, d.y, m10 * d.x),
+                                          __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
+            const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
+            dec_tile<METHOD, P, STATS>(al, D.grid, W, Bz, L, tile, f, fc);
+        }
+    }
+    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
+}
+
+
+// rgba[i] = decoder(xy[i]): 16 texels per MFMA tile, persistent waves; the
+// same per-row instruction sequence as the filter's decode.
 template <int P>
-__global__ __launch_bounds__(256, 2) void k_decoder_eval(DecArgs D, const int2* __restrict__ xy, int64_t n,
-                                                         float4* __restrict__ out)
+__global__ __launch_bounds__(256, 2) void k_decoder_eval(DevDecoderWeights D, const int2* __restrict__ xy,
+                                                         int64_t n, float4* __restrict__ out)
 {
     const int lane = lane_id();
     const int j = lane & 15, g = lane >> 4;
@@ -358,27 +472,11 @@ __global__ __launch_bounds__(256, 2) void k_decoder_eval(DecArgs D, const int2* 
         const int64_t row = t * 16 + j;
         const bool valid = row < n;
         const int2 p = valid ? xy[row] : make_int2(0, 0);
-        LatentTap tap;
-        const f4 X = latent_features<P>(D.lat0, D.lat1, D.l0, D.l1, D.shift0, D.shift1, D.tex_w, p.x, p.y, g, tap);
-        const f4 y = mlp_forward<P>(W, Bz, X, nullptr, nullptr);
+        LatentFetch F;
+        latent_fetch(D.grid, p.x, p.y, g, F);
+        const f4 y = mlp_forward<P>(W, Bz, latent_combine<P>(F), nullptr, nullptr);
         if (g == 0 && valid) out[row] = make_float4(y[0], y[1], y[2], y[3]);
     }
-}
-
-DecArgs dec_args(const ctf_texture_s* t)
-{
-    const DevDecoderWeights& W = t->dec;
-    DecArgs d;
-    d.lat0 = W.lat0;
-    d.lat1 = W.lat1;
-    d.w = W.w1;
-    d.bias = W.bias;
-    d.l0 = W.l0;
-    d.l1 = W.l1;
-    d.shift0 = W.shift0;
-    d.shift1 = W.shift1;
-    d.tex_w = W.tex_w;
-    return d;
 }
 
 int device_cus()
@@ -388,23 +486,37 @@ int device_cus()
     return cus > 0 ? cus : 256;
 }
 
-template <int METHOD, int P>
-hipError_t launch_dec(const FilterArgs& a, const DecArgs& d, hipStream_t s)
+// Persistent grid: as many workgroups as fit on the device at once (from the
+// kernel's register and LDS use), a multiple of the 8 XCDs.
+template <typename K>
+int64_t resident_blocks(K kernel, int threads, int64_t work_blocks)
 {
-    // persistent grid: up to 2 workgroups per CU, a multiple of the 8 XCDs
-    int64_t blocks = (a.ntiles + kDecWaves - 1) / kDecWaves;
-    const int64_t cap = (int64_t)device_cus() * 2;
-    if (blocks > cap) blocks = cap;
-    blocks = (blocks + 7) / 8 * 8;
-    if (a.tile_stats)
-        hipLaunchKernelGGL((k_filter_dec<METHOD, P, true>), dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
-    else
-        hipLaunchKernelGGL((k_filter_dec<METHOD, P, false>), dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int64_t blocks = (int64_t)device_cus() * per_cu;
+    if (blocks > work_blocks) blocks = work_blocks;
+    return (blocks + 7) / 8 * 8;
+}
+
+template <int METHOD, int P>
+hipError_t launch_dec(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
+{
+    const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+    if (a.tile_stats) {
+        auto k = k_filter_dec<METHOD, P, true>;
+        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    } else {
+        auto k = k_filter_dec<METHOD, P, false>;
+        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    }
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_dec_p(const FilterArgs& a, const DecArgs& d, hipStream_t s)
+hipError_t launch_dec_p(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
 {
     switch (a.method) {
     case CTF_BILINEAR4: return launch_dec<CTF_BILINEAR4, P>(a, d, s);
@@ -424,15 +536,55 @@ using namespace ctf;
 
 hipError_t ctf_internal_decoder_filter(const ctf_texture_s* t, const FilterArgs& a, hipStream_t s)
 {
-    const DecArgs d = dec_args(t);
+    const DevDecoderWeights& d = t->dec;
     return t->dec.precision == CTF_BF16 ? launch_dec_p<CTF_BF16>(a, d, s) : launch_dec_p<CTF_FP16>(a, d, s);
+}
+
+hipError_t ctf_internal_filter_layers(const ctf_texture_s* const* texs, const float* xforms, int n,
+                                      const FilterArgs& a, hipStream_t s)
+{
+    if (n < 1 || n > kMaxLayers) return hipErrorInvalidValue;
+    LayerSet LS;
+    LS.n = n;
+    const int prec = texs[0]->dec.precision;
+    for (int l = 0; l < n; ++l) {
+        if (texs[l]->dev.kind != CTF_TEX_DECODER || texs[l]->dec.precision != prec) return hipErrorInvalidValue;
+        LS.dec[l] = texs[l]->dec;
+        for (int k = 0; k < 4; ++k) LS.xf[l][k] = xforms[4 * l + k];
+    }
+    const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+    auto go = [&](auto kernel) {
+        const int64_t blocks = resident_blocks(kernel, 64 * kDecWaves, work);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
+        return hipGetLastError();
+    };
+    const bool st = a.tile_stats != nullptr;
+    const bool bf = prec == CTF_BF16;
+    switch (a.method) {
+    case CTF_BILINEAR4:
+        return bf ? (st ? go(k_filter_layers<CTF_BILINEAR4, CTF_BF16, true>) : go(k_filter_layers<CTF_BILINEAR4, CTF_BF16, false>))
+                  : (st ? go(k_filter_layers<CTF_BILINEAR4, CTF_FP16, true>) : go(k_filter_layers<CTF_BILINEAR4, CTF_FP16, false>));
+    case CTF_LIST:
+        return bf ? (st ? go(k_filter_layers<CTF_LIST, CTF_BF16, true>) : go(k_filter_layers<CTF_LIST, CTF_BF16, false>))
+                  : (st ? go(k_filter_layers<CTF_LIST, CTF_FP16, true>) : go(k_filter_layers<CTF_LIST, CTF_FP16, false>));
+    case CTF_BOX:
+        return bf ? (st ? go(k_filter_layers<CTF_BOX, CTF_BF16, true>) : go(k_filter_layers<CTF_BOX, CTF_BF16, false>))
+                  : (st ? go(k_filter_layers<CTF_BOX, CTF_FP16, true>) : go(k_filter_layers<CTF_BOX, CTF_FP16, false>));
+    case CTF_MASK:
+        return bf ? (st ? go(k_filter_layers<CTF_MASK, CTF_BF16, true>) : go(k_filter_layers<CTF_MASK, CTF_BF16, false>))
+                  : (st ? go(k_filter_layers<CTF_MASK, CTF_FP16, true>) : go(k_filter_layers<CTF_MASK, CTF_FP16, false>));
+    case CTF_STF1:
+        return bf ? (st ? go(k_filter_layers<CTF_STF1, CTF_BF16, true>) : go(k_filter_layers<CTF_STF1, CTF_BF16, false>))
+                  : (st ? go(k_filter_layers<CTF_STF1, CTF_FP16, true>) : go(k_filter_layers<CTF_STF1, CTF_FP16, false>));
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t ctf_internal_decoder_eval(const ctf_texture_s* t, const int32_t* xy, int64_t n, float* out,
                                      hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const DecArgs d = dec_args(t);
+    const DevDecoderWeights& d = t->dec;
     int64_t blocks = ((n + 15) / 16 + 3) / 4;
     const int64_t cap = (int64_t)device_cus() * 2;
     if (blocks > cap) blocks = cap;

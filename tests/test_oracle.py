@@ -416,3 +416,97 @@ def test_decoder_gradient_finite_differences_4x4_width4():
         fd[i] = (lp - lm) / (2 * eps)
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-8)
     assert np.abs(g).max() > 1e-3
+
+
+def test_layer_transform_identity_and_power_of_two_scale(c0_scene):
+    """The layer transform is a float32 map: the identity changes nothing,
+    and a power-of-two scale equals filtering pre-scaled coordinates."""
+    sc = c0_scene
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=0)
+    tex = O.sinusoid_texture(64, pqj, amp)
+    m = O.method(O.LIST, k=2)
+    base = O.filter(sc.uv, sc.duv, tex, m, seed=4, stf=True)
+    ident = O.filter(sc.uv, sc.duv, tex, m, seed=4, stf=True, xform=np.eye(2))
+    assert np.array_equal(base["out"], ident["out"]) and np.array_equal(base["stf"], ident["stf"])
+    two = O.filter(sc.uv, sc.duv, tex, m, seed=4, stf=True, xform=2 * np.eye(2))
+    pre = O.filter(sc.uv * np.float32(2), sc.duv * np.float32(2), tex, m, seed=4, stf=True)
+    assert np.array_equal(two["out"], pre["out"]) and np.array_equal(two["stf"], pre["stf"])
+    for f in ("part", "mask", "n", "evals"):
+        assert np.array_equal(two["stats"][f], pre["stats"][f])
+
+
+# ---------------------------------------------------------------------------
+# fallbacks C and C+ (Section 3.4)
+# ---------------------------------------------------------------------------
+
+def test_eq2_lane_mapping_pins():
+    g = GOLD["fallback_eq2"]
+    for nA, ns, c, want in g["cases"]:
+        assert O.cplus_target(nA, ns, c) == want, (nA, ns, c)
+    # the paper's formula written with exact rationals, round half up
+    from fractions import Fraction
+    for nA in (8, 32, 64):
+        for ns in range(nA):
+            for c in range(ns, nA):
+                want = 0 if nA - 1 - ns == 0 else int(Fraction((nA - 1) * (c - ns), nA - 1 - ns) + Fraction(1, 2))
+                assert O.cplus_target(nA, ns, c) == want
+            if nA - ns >= 2:
+                assert O.cplus_target(nA, ns, ns) == 0 and O.cplus_target(nA, ns, nA - 1) == nA - 1
+
+
+def _lowmag_scene():
+    """Head-on rotated quads at magnification ~1.0-1.3 with 8x8 tiles: exact
+    sets overflow one texel per lane, so the fallback runs on most tiles."""
+    rng = np.random.default_rng(21)
+    n = 600
+    mags = rng.uniform(1.0, 1.3, n)
+    angs = rng.uniform(0, np.pi / 2, n)
+    offs = rng.uniform(0, 64, (n, 2))
+    uv = np.zeros((8, 8 * n, 2), np.float32)
+    for i in range(n):
+        u, _ = cs.head_on_quad_uv(8, 8, mags[i], angs[i], offs[i], tex_w=64)
+        uv[:, 8 * i:8 * i + 8] = u
+    return uv, np.zeros(uv.shape[:2] + (4,), np.float32)
+
+
+@pytest.mark.parametrize("fb", [O.FB_C, O.FB_CPLUS])
+def test_eq1_special_cases(fb):
+    g = GOLD["fallback_eq1"]
+    assert g
+    uv, duv = _lowmag_scene()
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=7)
+    tex = O.sinusoid_texture(64, pqj, amp)
+    fbr = O.filter(uv, duv, tex, O.method(O.MASK, fallback=fb), seed=5, stf=True)
+    ex = O.filter(uv, duv, tex, O.method(O.BILINEAR4), seed=5)
+    st = O.filter(uv, duv, tex, O.method(O.MASK), seed=5, stf=True)
+    failed = (fbr["stats"]["flags"] & O.TILE_OK) == 0
+    assert failed.mean() > 0.5
+    # constant textures stay constant under Eq. 1
+    ct = O.filter(uv, duv, O.constant_texture(64, 64, (0.3, 0.6, 0.9, 1.0)),
+                  O.method(O.MASK, fallback=fb), seed=5)
+    assert np.allclose(ct["out"], [0.3, 0.6, 0.9, 1.0], atol=1e-15)
+    # lanes whose output equals the exact filter or the one-tap value
+    close_exact = np.abs(fbr["out"] - ex["out"]).max(-1) < 1e-12
+    close_stf = np.abs(fbr["out"] - st["out"]).max(-1) < 1e-12
+    drew = fbr["stf"][..., 0] != np.iinfo(np.int32).min
+    assert np.all(close_exact | close_stf | drew)
+    assert close_exact[drew].mean() > 0.05 and close_stf[drew].mean() > 0.005
+    # the draws themselves are the one-tap draws
+    assert np.array_equal(fbr["stf"], st["stf"])
+
+
+def test_fallback_quality_order():
+    """C+ is closer to exact filtering than C, and C closer than one-tap STF."""
+    assert GOLD["fallback_quality_order"]
+    uv, duv = _lowmag_scene()
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=8)
+    tex = O.sinusoid_texture(64, pqj, amp)
+    ex = O.filter(uv, duv, tex, O.method(O.BILINEAR4))["out"]
+    mse = {}
+    for name, fb in (("stf", O.FB_STF1), ("c", O.FB_C), ("cplus", O.FB_CPLUS)):
+        errs = []
+        for seed in range(4):
+            o = O.filter(uv, duv, tex, O.method(O.MASK, fallback=fb), seed=seed)["out"]
+            errs.append(((o - ex) ** 2).mean())
+        mse[name] = np.mean(errs)
+    assert mse["cplus"] < mse["c"] < mse["stf"], mse
