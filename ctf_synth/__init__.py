@@ -305,6 +305,23 @@ def head_on_quad_uv(tile_w, tile_h, magnification, angle_rad, offset, tex_w=4096
     return uv, duv
 
 
+def lowmag_quads_scene(n_tiles=600, seed=21, tex_w=64, mag=(1.0, 1.3)):
+    """A row of n_tiles 8x8 tiles, each a head-on quad at magnification drawn
+    from ``mag`` with a random rotation and offset (zero derivatives).  Near
+    magnification 1 an 8x8 tile needs more distinct texels than it has
+    lanes, so waves with one evaluation per lane fail and take the fallback.
+    Returns (uv [8][8 n][2], duv [8][8 n][4]) float32."""
+    rng = np.random.default_rng(seed)
+    mags = rng.uniform(mag[0], mag[1], n_tiles)
+    angs = rng.uniform(0, math.pi / 2, n_tiles)
+    offs = rng.uniform(0, tex_w, (n_tiles, 2))
+    uv = np.zeros((8, 8 * n_tiles, 2), np.float32)
+    for i in range(n_tiles):
+        u, _ = head_on_quad_uv(8, 8, mags[i], angs[i], offs[i], tex_w=tex_w)
+        uv[:, 8 * i:8 * i + 8] = u
+    return uv, np.zeros(uv.shape[:2] + (4,), np.float32)
+
+
 # ---------------------------------------------------------------------------
 # decoder parameters
 # ---------------------------------------------------------------------------

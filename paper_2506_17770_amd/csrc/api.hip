@@ -234,7 +234,8 @@ static ctf_status check_method(const ctf_method* m, const char* who)
     if (m->kind == CTF_MASK && m->mask_side != 16)
         return fail(CTF_ERR_UNSUPPORTED, "%s: mask_side %d (16 is built)", who, m->mask_side);
     if (m->box_w < 0 || m->box_h < 0) return fail(CTF_ERR_INVALID_ARG, "%s: negative box budget", who);
-    if (m->fallback != CTF_FB_STF1) return fail(CTF_ERR_UNSUPPORTED, "%s: fallback %d not built", who, m->fallback);
+    if (m->fallback < CTF_FB_STF1 || m->fallback > CTF_FB_CPLUS)
+        return fail(CTF_ERR_INVALID_ARG, "%s: unknown fallback %d", who, m->fallback);
     return CTF_OK;
 }
 
@@ -254,6 +255,7 @@ static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int
     a.box_w = m->box_w;
     a.box_h = m->box_h;
     a.max_evals = m->max_evals_per_lane;
+    a.fallback = m->fallback;
     a.seed = seed;
     a.layer = 0;
     a.tile_stats = ts;

@@ -139,17 +139,43 @@ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
     return (word >> 22u) ^ word;
 }
 
-__device__ __forceinline__ int2 stf_pick(const Footprint& f, uint64_t seed, uint32_t layer,
-                                         int px, int py)
+// The per-pixel hash chain of the one-tap draws: h1 and h2 choose the texel
+// of the footprint (stf_pick); h3 = pcg(h2) is the spare-lane choice of
+// fallback C+.
+__device__ __forceinline__ void stf_hashes(uint64_t seed, uint32_t layer, int px, int py, uint32_t& h1,
+                                           uint32_t& h2)
 {
     uint32_t h = pcg_hash(layer ^ (uint32_t)(seed >> 32));
     h = pcg_hash((uint32_t)py ^ h);
     h = pcg_hash((uint32_t)px ^ h);
-    const uint32_t h1 = pcg_hash((uint32_t)seed ^ h);
-    const uint32_t h2 = pcg_hash(h1);
+    h1 = pcg_hash((uint32_t)seed ^ h);
+    h2 = pcg_hash(h1);
+}
+
+__device__ __forceinline__ int2 stf_pick_h(const Footprint& f, uint32_t h1, uint32_t h2)
+{
     const float u1 = (float)(h1 >> 8) * 0x1p-24f;
     const float u2 = (float)(h2 >> 8) * 0x1p-24f;
     return make_int2(f.x0 + (u1 < f.s ? 1 : 0), f.y0 + (u2 < f.t ? 1 : 0));
+}
+
+__device__ __forceinline__ int2 stf_pick(const Footprint& f, uint64_t seed, uint32_t layer,
+                                         int px, int py)
+{
+    uint32_t h1, h2;
+    stf_hashes(seed, layer, px, py, h1, h2);
+    return stf_pick_h(f, h1, h2);
+}
+
+// 256-bit footprint mask from the mask of footprint corners:
+// B = C | C<<1 | C<<16 | C<<17 (words low first; wave-uniform, scalar ops).
+__device__ __forceinline__ void footprint_mask(const uint64_t C[4], uint64_t B[4])
+{
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint64_t lo = w > 0 ? C[w - 1] : 0ull;
+        B[w] = C[w] | (C[w] << 1) | (lo >> 63) | (C[w] << 16) | (lo >> 48) | (C[w] << 17) | (lo >> 47);
+    }
 }
 
 // Frame totals of one wave over all its tiles, added to the frame record

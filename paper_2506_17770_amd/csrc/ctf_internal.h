@@ -22,6 +22,7 @@ struct FilterArgs {
     int method;
     int box_w, box_h;
     int max_evals;
+    int fallback;               // CTF_FB_* for the lanes of a failed wave
     uint64_t seed;
     uint32_t layer;
     ctf_tile_stats* tile_stats;

@@ -1,10 +1,11 @@
 // filter_decoder.hip -- collaborative filtering with the learned texel producer.
 //
 // Same decisions as the per-lane path (Sections 3.1-3.3, remapping and the
-// one-tap fallback), but texel production is batched: the wave writes the
-// (x, y) of every texel it must produce into an LDS row list (the unique
-// texels first, then one row per fallback draw) and decodes the rows 16 at
-// a time on MFMA (decoder_mlp.h).  Dedup therefore turns the 4-texel
+// fallbacks of Section 3.4), but texel production is batched: the wave
+// writes the (x, y) of every texel it must produce into an LDS row list
+// (the unique texels first, then one row per one-tap draw; in a wave that
+// takes fallback C or C+, the planned texels of A, then the minifying
+// lanes' draws) and decodes the rows 16 at a time on MFMA (decoder_mlp.h).  Dedup therefore turns the 4-texel
 // bilinear decode into one dense MLP pass over the wave's distinct texels.
 //
 // Waves are persistent: each loads the MLP weights into registers once and
@@ -14,6 +15,7 @@
 #include "ctf_device.h"
 #include "ctf_internal.h"
 #include "decoder_mlp.h"
+#include "fallback.h"
 
 namespace ctf {
 
@@ -22,12 +24,11 @@ namespace {
 constexpr int kDecWaves = 4;
 
 struct DecLds {
-    float4 vals[kMaxItems];
-    int2 rows[kMaxItems];
-    uint64_t keys[kMaxItems];
-    uint16_t items[kMaxItems];
-    uint8_t rank[256];
-    uint8_t bytes[256];
+    float4 vals[kMaxItems];     // decoded texels, by row
+    int2 rows[kMaxItems];       // texel coordinates to decode
+    uint64_t keys[kMaxItems];   // List past 16x16: sorted unique keys
+    uint8_t rank[256];          // Mask/List: position t -> row (h^-1)
+    uint8_t bytes[256];         // footprint-corner scatter before the ballots
 };
 
 
@@ -130,7 +131,7 @@ __device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& 
 // gather and outputs.  `f` is the lanes' footprint (already in this
 // layer's coordinates); a.out / a.tile_stats / a.stf_xy point at this
 // layer's planes.
-template <int METHOD, int P, bool STATS>
+template <int METHOD, int P, bool STATS, bool FB>
 __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& G, const FwdWeights<P>& W,
                                          const Biases& Bz, DecLds& L, int64_t tile, const Footprint& f,
                                          FrameCounters& fc)
@@ -156,34 +157,24 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
     }
     const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
 
+    // ---- 16x16 wave mask B (Mask Sampling; also the exact set when it
+    // fits).  Each lane of A marks only its footprint's upper-left texel
+    // (mask C, one LDS byte and four ballots); every footprint adds the
+    // texels at +1, +16 and +17, so B = C | C<<1 | C<<16 | C<<17 (rows of
+    // 16 do not wrap: corners have dx, dy <= 14 when the box fits).
     uint64_t B[4] = {0, 0, 0, 0};
     int nmask = 0;
     constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
     if (kNeedMask && fits16) {
         reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
         wave_lds_sync();
-        if (inA) {
-            const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-            L.bytes[t] = 1;
-            L.bytes[t + 1] = 1;
-            L.bytes[t + 16] = 1;
-            L.bytes[t + 17] = 1;
-        }
+        if (inA) L.bytes[16 * (f.y0 - ymin) + (f.x0 - xmin)] = 1;
         wave_lds_sync();
+        uint64_t C[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) B[w] = ballot(L.bytes[64 * w + lane] != 0);
-        int base = 0;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            if ((B[w] >> lane) & 1u) {
-                const int r = base + mbcnt(B[w]);
-                L.items[r] = (uint16_t)(64 * w + lane);
-                L.rank[64 * w + lane] = (uint8_t)r;
-            }
-            base += popc64(B[w]);
-        }
-        nmask = base;
-        wave_lds_sync();
+        for (int w = 0; w < 4; ++w) C[w] = ballot(L.bytes[64 * w + lane] != 0);
+        footprint_mask(C, B);
+        nmask = popc64(B[0]) + popc64(B[1]) + popc64(B[2]) + popc64(B[3]);
     }
 
     const int k = a.max_evals;
@@ -231,9 +222,19 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
     const uint64_t stfmask = ballot(draws);
     const int nstf = popc64(stfmask);
     int2 pick = make_int2(INT32_MIN, INT32_MIN);
-    if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
+    uint32_t h1 = 0, h2 = 0;
+    if (draws) {
+        stf_hashes(a.seed, a.layer, px, py, h1, h2);
+        pick = stf_pick_h(f, h1, h2);
+    }
+    // fallback C / C+ for the lanes of A of a failed wave (fallback.h)
+    const bool fallback = FB && !success && nA > 0;
+    const uint64_t mdraw = stfmask & ~A;   // minifying draws in a fallback wave
+    FallbackPlan fp{};
 
-    // ---- row list: the texels to produce
+    // ---- row list: the texels to produce (unique texels first, in the
+    // method's order, then one row per fallback draw) and the inverse table
+    // of Mask/List
     const int rank_act = mbcnt(act);
     const int ns = success ? n : 0;
     int R;
@@ -243,26 +244,44 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
 #pragma unroll
             for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
         }
+    } else if (fallback) {
+        fp = plan_fallback(L, a.fallback, inA, nA, mbcnt(A), f, pick, pcg_hash(h2), fits16, xmin, ymin);
+        R = fp.nprod + popc64(mdraw);
+        if (fp.produces) L.rows[fp.slot] = fp.texel;
+        if (draws && !inA) L.rows[fp.nprod + mbcnt(mdraw)] = pick;
     } else {
         R = ns + nstf;
-        for (int i = lane; i < ns; i += kWave) {
-            int ex, ey;
-            if constexpr (METHOD == CTF_BOX) {
-                ex = xmin + i % bbw;
-                ey = ymin + i / bbw;
+        if (success) {
+            if (METHOD == CTF_BOX || sorted) {
+                for (int i = lane; i < ns; i += kWave) {
+                    int ex, ey;
+                    if (METHOD == CTF_BOX) {
+                        ex = xmin + i % bbw;
+                        ey = ymin + i / bbw;
+                    } else {
+                        const uint64_t key = L.keys[i];
+                        ex = xmin + (int)(uint32_t)key;
+                        ey = ymin + (int)(key >> 32);
+                    }
+                    L.rows[i] = make_int2(ex, ey);
+                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+                }
             } else {
-                if (sorted) {
-                    const uint64_t key = L.keys[i];
-                    ex = xmin + (int)(uint32_t)key;
-                    ey = ymin + (int)(key >> 32);
-                } else {
-                    const int t = L.items[i];
-                    ex = xmin + (t & 15);
-                    ey = ymin + (t >> 4);
+                // set bit t of B with rank r: row r, and rank[t] = r (h^-1)
+                int base = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if ((B[w] >> lane) & 1u) {
+                        const int r = base + mbcnt(B[w]);
+                        const int t = 64 * w + lane;
+                        const int2 c = make_int2(xmin + (t & 15), ymin + (t >> 4));
+                        L.rank[t] = (uint8_t)r;
+                        L.rows[r] = c;
+                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
+                    }
+                    base += popc64(B[w]);
                 }
             }
-            L.rows[i] = make_int2(ex, ey);
-            if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
         }
         if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
     }
@@ -273,6 +292,32 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
     decode_rows<P>(L, R, G, W, Bz, j, g);
     wave_lds_sync();
 
+    int idx[4] = {0, 0, 0, 0};
+    if constexpr (kCollab) {
+        if (exact) {
+            if constexpr (METHOD == CTF_BOX) {
+                const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
+                idx[0] = b;
+                idx[1] = b + 1;
+                idx[2] = b + bbw;
+                idx[3] = b + bbw + 1;
+            } else if (sorted) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
+                                         (uint32_t)(f.x0 + (q & 1) - xmin);
+                    idx[q] = dec_list_find(L, n, key);
+                }
+            } else {
+                const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
+                idx[0] = L.rank[t];
+                idx[1] = L.rank[t + 1];
+                idx[2] = L.rank[t + 16];
+                idx[3] = L.rank[t + 17];
+            }
+        }
+    }
+
     // ---- gather and weight
     float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (METHOD == CTF_BILINEAR4) {
@@ -280,34 +325,13 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
             const int b = 4 * rank_act;
             res = bilerp(f.s, f.t, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
         }
+    } else if (fallback) {
+        if (draws && !inA) res = L.vals[fp.nprod + mbcnt(mdraw)];
+        if (inA) res = fallback_color(L, fp, f, pick, xmin, ymin);
     } else {
         if (draws) res = L.vals[ns + mbcnt(stfmask)];
-        if constexpr (kCollab) {
-            if (exact) {
-                int idx[4];
-                if constexpr (METHOD == CTF_BOX) {
-                    const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
-                    idx[0] = b;
-                    idx[1] = b + 1;
-                    idx[2] = b + bbw;
-                    idx[3] = b + bbw + 1;
-                } else if (sorted) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                             (uint32_t)(f.x0 + (q & 1) - xmin);
-                        idx[q] = dec_list_find(L, n, key);
-                    }
-                } else {
-                    const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                    idx[0] = L.rank[t];
-                    idx[1] = L.rank[t + 1];
-                    idx[2] = L.rank[t + 16];
-                    idx[3] = L.rank[t + 17];
-                }
-                res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
-            }
-        }
+        if (kCollab && exact)
+            res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
     }
     if (in_screen) {
         reinterpret_cast<float4*>(a.out)[pix] = res;
@@ -369,7 +393,7 @@ struct Band {
     }
 };
 
-template <int METHOD, int P, bool STATS>
+template <int METHOD, int P, bool STATS, bool FB>
 __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, DevDecoderWeights D)
 {
     __shared__ DecLds lds_all[kDecWaves];
@@ -393,7 +417,7 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, 
         const float4 d = d_next;
         load_tile_px(a, tile + band.nw, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
-        dec_tile<METHOD, P, STATS>(a, D.grid, W, Bz, L, tile, f, fc);
+        dec_tile<METHOD, P, STATS, FB>(a, D.grid, W, Bz, L, tile, f, fc);
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
@@ -410,7 +434,7 @@ struct LayerSet {
     int n;
 };
 
-template <int METHOD, int P, bool STATS>
+template <int METHOD, int P, bool STATS, bool FB>
 __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_layers(FilterArgs a, LayerSet LS)
 {
     __shared__ DecLds lds_all[kDecWaves];
@@ -446,7 +470,7 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_layers(FilterArgs 
             const float4 ld = make_float4(__builtin_fmaf(m01, d.y, m00 * d.x), __builtin_fmaf(m11, d.y, m10 * d.x),
                                           __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
             const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
-            dec_tile<METHOD, P, STATS>(al, D.grid, W, Bz, L, tile, f, fc);
+            dec_tile<METHOD, P, STATS, FB>(al, D.grid, W, Bz, L, tile, f, fc);
         }
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
@@ -499,20 +523,69 @@ int64_t resident_blocks(K kernel, int threads, int64_t work_blocks)
     return (blocks + 7) / 8 * 8;
 }
 
+constexpr bool collaborative(int m) { return m == CTF_LIST || m == CTF_BOX || m == CTF_MASK; }
+
+// Instantiation for the call's statistics and fallback flags; waves of a
+// collaborative method carry the C / C+ code only when it is asked for, so
+// the common path keeps its register budget.
+template <int METHOD, int P, template <int, int, bool, bool> class Go, class... Args>
+hipError_t dispatch_flags(const FilterArgs& a, Args&&... args)
+{
+    const bool st = a.tile_stats != nullptr;
+    if constexpr (collaborative(METHOD)) {
+        if (a.fallback != CTF_FB_STF1)
+            return st ? Go<METHOD, P, true, true>::run(a, args...) : Go<METHOD, P, false, true>::run(a, args...);
+    }
+    return st ? Go<METHOD, P, true, false>::run(a, args...) : Go<METHOD, P, false, false>::run(a, args...);
+}
+
+template <int METHOD, int P, bool STATS, bool FB>
+struct GoFilter {
+    static hipError_t run(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
+    {
+        const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+        auto k = k_filter_dec<METHOD, P, STATS, FB>;
+        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+        return hipGetLastError();
+    }
+};
+
+template <int METHOD, int P, bool STATS, bool FB>
+struct GoLayers {
+    static hipError_t run(const FilterArgs& a, const LayerSet& LS, hipStream_t s)
+    {
+        const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+        auto k = k_filter_layers<METHOD, P, STATS, FB>;
+        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
+        return hipGetLastError();
+    }
+};
+
 template <int METHOD, int P>
 hipError_t launch_dec(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
 {
-    const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
-    if (a.tile_stats) {
-        auto k = k_filter_dec<METHOD, P, true>;
-        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
-    } else {
-        auto k = k_filter_dec<METHOD, P, false>;
-        const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+    return dispatch_flags<METHOD, P, GoFilter>(a, d, s);
+}
+
+template <int METHOD, int P>
+hipError_t launch_layers(const FilterArgs& a, const LayerSet& LS, hipStream_t s)
+{
+    return dispatch_flags<METHOD, P, GoLayers>(a, LS, s);
+}
+
+template <int P>
+hipError_t launch_layers_p(const FilterArgs& a, const LayerSet& LS, hipStream_t s)
+{
+    switch (a.method) {
+    case CTF_BILINEAR4: return launch_layers<CTF_BILINEAR4, P>(a, LS, s);
+    case CTF_STF1: return launch_layers<CTF_STF1, P>(a, LS, s);
+    case CTF_LIST: return launch_layers<CTF_LIST, P>(a, LS, s);
+    case CTF_BOX: return launch_layers<CTF_BOX, P>(a, LS, s);
+    case CTF_MASK: return launch_layers<CTF_MASK, P>(a, LS, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int P>
@@ -552,32 +625,7 @@ hipError_t ctf_internal_filter_layers(const ctf_texture_s* const* texs, const fl
         LS.dec[l] = texs[l]->dec;
         for (int k = 0; k < 4; ++k) LS.xf[l][k] = xforms[4 * l + k];
     }
-    const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
-    auto go = [&](auto kernel) {
-        const int64_t blocks = resident_blocks(kernel, 64 * kDecWaves, work);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
-        return hipGetLastError();
-    };
-    const bool st = a.tile_stats != nullptr;
-    const bool bf = prec == CTF_BF16;
-    switch (a.method) {
-    case CTF_BILINEAR4:
-        return bf ? (st ? go(k_filter_layers<CTF_BILINEAR4, CTF_BF16, true>) : go(k_filter_layers<CTF_BILINEAR4, CTF_BF16, false>))
-                  : (st ? go(k_filter_layers<CTF_BILINEAR4, CTF_FP16, true>) : go(k_filter_layers<CTF_BILINEAR4, CTF_FP16, false>));
-    case CTF_LIST:
-        return bf ? (st ? go(k_filter_layers<CTF_LIST, CTF_BF16, true>) : go(k_filter_layers<CTF_LIST, CTF_BF16, false>))
-                  : (st ? go(k_filter_layers<CTF_LIST, CTF_FP16, true>) : go(k_filter_layers<CTF_LIST, CTF_FP16, false>));
-    case CTF_BOX:
-        return bf ? (st ? go(k_filter_layers<CTF_BOX, CTF_BF16, true>) : go(k_filter_layers<CTF_BOX, CTF_BF16, false>))
-                  : (st ? go(k_filter_layers<CTF_BOX, CTF_FP16, true>) : go(k_filter_layers<CTF_BOX, CTF_FP16, false>));
-    case CTF_MASK:
-        return bf ? (st ? go(k_filter_layers<CTF_MASK, CTF_BF16, true>) : go(k_filter_layers<CTF_MASK, CTF_BF16, false>))
-                  : (st ? go(k_filter_layers<CTF_MASK, CTF_FP16, true>) : go(k_filter_layers<CTF_MASK, CTF_FP16, false>));
-    case CTF_STF1:
-        return bf ? (st ? go(k_filter_layers<CTF_STF1, CTF_BF16, true>) : go(k_filter_layers<CTF_STF1, CTF_BF16, false>))
-                  : (st ? go(k_filter_layers<CTF_STF1, CTF_FP16, true>) : go(k_filter_layers<CTF_STF1, CTF_FP16, false>));
-    default: return hipErrorInvalidValue;
-    }
+    return prec == CTF_BF16 ? launch_layers_p<CTF_BF16>(a, LS, s) : launch_layers_p<CTF_FP16>(a, LS, s);
 }
 
 hipError_t ctf_internal_decoder_eval(const ctf_texture_s* t, const int32_t* xy, int64_t n, float* out,

@@ -8,10 +8,11 @@
 //
 // Paper: Section 3 (three-step flow), 3.1 List Merge, 3.2 Box Sampling,
 // 3.3 Mask Sampling (bijection h of Figure 3), supplement Section 2 (edge
-// remapping: item i is produced by lane h(i, A)), Section 3.4 (one-tap STF
-// fallback).
+// remapping: item i is produced by lane h(i, A)), Section 3.4 (fallbacks:
+// one-tap STF, C of Eq. 1 and C+ of Eq. 2, fallback.h).
 #include "ctf_device.h"
 #include "ctf_internal.h"
+#include "fallback.h"
 
 namespace ctf {
 
@@ -24,7 +25,7 @@ struct WaveLds {
     uint64_t keys[kMaxItems];   // List: sorted unique texel keys (dy << 32 | dx)
     uint16_t items[kMaxItems];  // Mask: item i -> mask position t = h(i, B)
     uint8_t rank[256];          // Mask: position t -> item index h^-1(t, B)
-    uint8_t bytes[256];         // Mask: footprint scatter before the ballots
+    uint8_t bytes[256];         // Mask: footprint-corner scatter before the ballots
 };
 
 // Exact set of the wave's texels as sorted unique keys (any box size): a
@@ -143,21 +144,19 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         int nmask = 0;
         constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
         if (kNeedMask && fits16) {
+            // corners of the footprints (mask C) by one LDS byte per lane and
+            // four ballots; B = C | C<<1 | C<<16 | C<<17
             reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
             wave_lds_sync();
-            if (inA) {
-                const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                L.bytes[t] = 1;
-                L.bytes[t + 1] = 1;
-                L.bytes[t + 16] = 1;
-                L.bytes[t + 17] = 1;
-            }
+            if (inA) L.bytes[16 * (f.y0 - ymin) + (f.x0 - xmin)] = 1;
             wave_lds_sync();
-    #pragma unroll
-            for (int w = 0; w < 4; ++w) B[w] = ballot(L.bytes[64 * w + lane] != 0);
+            uint64_t C[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) C[w] = ballot(L.bytes[64 * w + lane] != 0);
+            footprint_mask(C, B);
             // h and h^-1 as tables: set bit t of rank r gives items[r] = t, rank[t] = r
             int base = 0;
-    #pragma unroll
+#pragma unroll
             for (int w = 0; w < 4; ++w) {
                 if ((B[w] >> lane) & 1u) {
                     const int r = base + mbcnt(B[w]);
@@ -220,7 +219,15 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         // ---- texel production: each lane evaluates at most one texel per round
         float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
         int2 pick = make_int2(INT32_MIN, INT32_MIN);
-        if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
+        uint32_t h1 = 0, h2 = 0;
+        if (draws) {
+            stf_hashes(a.seed, a.layer, px, py, h1, h2);
+            pick = stf_pick_h(f, h1, h2);
+        }
+        // fallback C / C+ for the lanes of A of a failed wave
+        const bool fallback = kCollab && !success && nA > 0 && a.fallback != CTF_FB_STF1;
+        FallbackPlan P{};
+        if (fallback) P = plan_fallback(L, a.fallback, inA, nA, rankA, f, pick, pcg_hash(h2), fits16, xmin, ymin);
 
         if constexpr (METHOD == CTF_BILINEAR4) {
             if (exact) {
@@ -230,6 +237,17 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                 const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
                 res = bilerp(f.s, f.t, v0, v1, v2, v3);
             }
+        } else if (fallback) {
+            // lanes of A evaluate the planned texels; minifying lanes draw
+            const bool pa = inA && P.produces, pd = draws && !inA;
+            if (pa || pd) {
+                const int2 e = pa ? P.texel : pick;
+                const float4 v = texel_eval<TEX>(T, e.x, e.y);
+                if (pa) L.vals[P.slot] = v;
+                else res = v;
+            }
+            wave_lds_sync();
+            if (inA) res = fallback_color(L, P, f, pick, xmin, ymin);
         } else {
             for (int round = 0; round < (kCollab ? k : 1); ++round) {
                 const int item = rankA + round * nA;
@@ -277,7 +295,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                         idx[3] = b + bbw + 1;
                     } else {
                         if (sorted) {
-    #pragma unroll
+#pragma unroll
                             for (int q = 0; q < 4; ++q) {
                                 const uint64_t key =
                                     ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
@@ -307,6 +325,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         const int nstf = popc64(stfmask);
         int evals;
         if constexpr (METHOD == CTF_BILINEAR4) evals = 4 * popc64(act);
+        else if (fallback) evals = P.nprod + popc64(stfmask & ~A);
         else evals = (success ? n : 0) + nstf;
 
         if (lane == 0) {

@@ -455,18 +455,8 @@ def test_eq2_lane_mapping_pins():
 
 
 def _lowmag_scene():
-    """Head-on rotated quads at magnification ~1.0-1.3 with 8x8 tiles: exact
-    sets overflow one texel per lane, so the fallback runs on most tiles."""
-    rng = np.random.default_rng(21)
-    n = 600
-    mags = rng.uniform(1.0, 1.3, n)
-    angs = rng.uniform(0, np.pi / 2, n)
-    offs = rng.uniform(0, 64, (n, 2))
-    uv = np.zeros((8, 8 * n, 2), np.float32)
-    for i in range(n):
-        u, _ = cs.head_on_quad_uv(8, 8, mags[i], angs[i], offs[i], tex_w=64)
-        uv[:, 8 * i:8 * i + 8] = u
-    return uv, np.zeros(uv.shape[:2] + (4,), np.float32)
+    """Exact sets overflow one texel per lane: the fallback runs on most tiles."""
+    return cs.lowmag_quads_scene(600, seed=21, tex_w=64)
 
 
 @pytest.mark.parametrize("fb", [O.FB_C, O.FB_CPLUS])
