@@ -59,7 +59,16 @@ enum {
     CTF_MASK = 4        /* 16x16 texel bitmask (Section 3.3) */
 };
 
-/* Fallback for lanes whose wave cannot provide all their texels. */
+/* Fallback for the participating lanes of a wave whose collaborative step
+ * failed (Section 3.4).  Minifying lanes always take the one-tap draw.
+ *   CTF_FB_STF1:  each lane returns its one-tap STF texel.
+ *   CTF_FB_C:     each lane evaluates its one-tap texel; each lane then
+ *                 weights the evaluated texels of its footprint with Eq. 1.
+ *   CTF_FB_CPLUS: the distinct one-tap texels are evaluated once and the
+ *                 lanes left over evaluate one more texel each from the
+ *                 footprint of the lane Eq. 2 assigns them (weighted draw
+ *                 among its texels not yet evaluated); then Eq. 1.  Needs
+ *                 the wave box to fit 16x16, otherwise CTF_FB_C is used. */
 enum { CTF_FB_STF1 = 0, CTF_FB_C = 1, CTF_FB_CPLUS = 2 };
 
 /* Texel producers (Section 3: "produce a texel"). */
@@ -139,14 +148,14 @@ typedef struct ctf_method {
     int32_t box_w, box_h;        /* CTF_BOX per-axis budget; 0,0 = the paper's rule only */
     int32_t mask_side;           /* CTF_MASK: 16 */
     int32_t max_evals_per_lane;  /* k in 1..4: a wave succeeds when n <= k * |A| */
-    int32_t fallback;            /* CTF_FB_STF1 */
+    int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
 } ctf_method;
 
 /* One record per tile (128 bytes). */
 typedef struct ctf_tile_stats {
     uint64_t active;     /* bit l: lane l has a finite uv with |uv*dim| < 2^24 */
     uint64_t part;       /* A: active and magnifying (both screen-axis footprints <= 1 texel) */
-    uint64_t stf;        /* lanes whose output is a one-tap STF draw */
+    uint64_t stf;        /* lanes not filtered exactly: a one-tap draw, or fallback C / C+ */
     uint64_t mask[4];    /* 16x16 mask of A's texels relative to (xmin,ymin), bit t = 16 dy + dx
                             in word t/64; zero when the box exceeds 16x16 */
     int32_t xmin, ymin;  /* texel box of A (0 when A is empty) */
@@ -162,7 +171,7 @@ typedef struct ctf_tile_stats {
 typedef struct ctf_frame_stats {
     uint64_t evals;       /* texel evaluations */
     uint64_t active;      /* active pixels */
-    uint64_t stf;         /* pixels that took a fallback draw */
+    uint64_t stf;         /* pixels not filtered exactly (one-tap draw or fallback C / C+) */
     uint64_t minify;      /* active pixels that minify */
     uint64_t tiles;       /* tiles with at least one active pixel */
     uint64_t tiles_ok;    /* tiles whose collaborative step succeeded */
@@ -185,7 +194,8 @@ typedef struct ctf_frame_stats {
  *   int32 [tiles][256][2], the (x, y) of item i of every successful tile for
  *   i < n, in the method's order (Box: row-major box cells; Mask and List:
  *   (y, x)-ascending); debug_stf: nullable device int32 [sh][sw][2], the
- *   texel drawn by each STF pixel and INT32_MIN for other active pixels.
+ *   one-tap texel drawn by each pixel not filtered exactly (also those of
+ *   fallback C / C+) and INT32_MIN for the other active pixels.
  * Errors: CTF_ERR_INVALID_ARG (NULL buffers, non-positive sizes, bad method),
  * CTF_ERR_UNSUPPORTED (method/texture combination not built). */
 ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
@@ -206,7 +216,7 @@ ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
  * [n_layers][tiles]; debug_stf: nullable device int32 [n_layers][sh][sw][2];
  * frame_stats: nullable, totals over all layers.  Other arguments as for
  * ctf_filter.  Errors: CTF_ERR_INVALID_ARG, CTF_ERR_UNSUPPORTED (non-decoder
- * texture, mixed precisions, fallback other than CTF_FB_STF1). */
+ * texture, mixed precisions). */
 ctf_status ctf_filter_layers(ctf_context ctx, const float *uv, const float *uv_derivs,
                              int32_t sw, int32_t sh, int32_t n_layers, const ctf_texture *texs,
                              const float *xforms, const ctf_method *method, uint64_t seed,
