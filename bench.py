@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp16", "bf16"], default="fp16")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (scale for the HBM byte counters)")
+    ap.add_argument("--no-procedural", action="store_true", help="skip the 1080p procedural-texture runs")
+    ap.add_argument("--no-layers", action="store_true", help="skip the six-layer 4K runs")
+    ap.add_argument("--layers", type=int, default=6)
     return ap.parse_args()
 
 
@@ -125,6 +128,106 @@ def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed):
     return {"value": px / dt / 1e9, "unit": "Gpixels/s", "cores": len(ths), "kind": "oracle",
             "sample": f"{len(starts) * 64} of {ntiles} 8x8 tiles of the same frame (runs of 64 tiles), "
                       f"float64 decoder, List k=4 + STF, {dt:.1f} s wall"}
+
+
+def bench_procedural(ctx, ctf, cs, torch, args, stream):
+    """1920x1080 four-plane frame, 2048^2 procedural texture (32 sinusoids per
+    channel): every method through the per-lane kernel."""
+    sc = cs.random_planes_scene(1920, 1080, 2048, 2048, seed=1)
+    pqj, amp = cs.sinusoid_params(2048, 32, 64, seed=2)
+    tex = ctx.sinusoid_texture(2048, pqj, amp)
+    uv = torch.from_numpy(sc.uv).cuda()
+    duv = torch.from_numpy(sc.duv).cuda()
+    out = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    npx = 1920 * 1080
+    res = {}
+    for name, m in (("bilinear4", ctf.method(ctf.BILINEAR4)), ("stf1", ctf.method(ctf.STF1)),
+                    ("list", ctf.method(ctf.LIST)), ("box4x4", ctf.method(ctf.BOX, box=(4, 4))),
+                    ("box6x6", ctf.method(ctf.BOX, box=(6, 6))), ("mask", ctf.method(ctf.MASK)),
+                    ("mask_fbC", ctf.method(ctf.MASK, fallback=ctf.FB_C)),
+                    ("mask_fbCplus", ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS)),
+                    ("list_k2", ctf.method(ctf.LIST, k=2))):
+        fs = ctf.frame_stats_buffer()
+        ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs)
+        torch.cuda.synchronize()
+        st = ctf.frame_stats_dict(fs)
+        _, per = timed(lambda: ctx.filter(uv, duv, tex, m, out=out), stream, max(3, args.steps // 2), 2, torch)
+        ms = float(np.mean(per))
+        res[name] = {"gpixels_per_s": npx / (ms * 1e-3) / 1e9, "ms": ms,
+                     "texel_evals_per_pixel": st["evals"] / npx,
+                     "not_exact_fraction": st["stf"] / max(1, st["active"]),
+                     "waves_failed": st["tiles_fail"], "waves_ok": st["tiles_ok"]}
+    b4 = res["bilinear4"]["gpixels_per_s"]
+    for v in res.values():
+        v["speedup_vs_bilinear4"] = v["gpixels_per_s"] / b4
+    tex.close()
+    return {"workload": "1920x1080 four-plane frame, 2048^2 procedural texture (K=32 sinusoids "
+                        "per channel, F=64), per-lane texel production", "methods": res}
+
+
+def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
+    """Six material layers at 4K in one launch: layer l has its own texture
+    (seed 11 + l) and decoder, and samples uv_l = s_l R(theta_l) uv."""
+    n = args.layers
+    tex_w, l0, l1, H = 2048, 512, 128, 64
+    decs, psnr = [], {"fp16": [], "bf16": []}
+    ys, xs = np.mgrid[0:tex_w, 0:tex_w]
+    xy = torch.from_numpy(np.stack([xs.ravel(), ys.ravel()], -1).astype(np.int32)).cuda()
+    fp_bf_max = []
+    t0 = time.perf_counter()
+    for l in range(n):
+        pqj, amp = cs.sinusoid_params(tex_w, 32, 64, seed=11 + l)
+        target = ctx.sinusoid_texture(tex_w, pqj, amp)
+        dec = ctx.decoder(l0, l1, H, tex_w, cs.decoder_init(l0, l1, H, seed=100 + l))
+        if args.train_steps:
+            dec.train(target, args.train_steps, batch=args.batch, lr=1e-3, seed=200 + l, precision=ctf.BF16)
+        pv = target.eval(xy).double()
+        vals = {}
+        for pname, prec in (("fp16", ctf.FP16), ("bf16", ctf.BF16)):
+            t = ctx.decoder_texture(dec, prec)
+            vals[pname] = t.eval(xy)
+            mse = float(((vals[pname].double() - pv) ** 2).mean())
+            psnr[pname].append(10 * math.log10(1.0 / mse))
+            t.close()
+        fp_bf_max.append(float((vals["fp16"] - vals["bf16"]).abs().max()))
+        del vals, pv
+        target.close()
+        decs.append(dec)
+    train_s = time.perf_counter() - t0
+    del xy
+    mats = np.array([cs.layer_params(11, l)[2] for l in range(n)], np.float32)
+    scales = [float(cs.layer_params(11, l)[0]) for l in range(n)]
+    out = torch.empty((n, args.height, args.width, 4), dtype=torch.float32, device="cuda")
+    npx = args.width * args.height
+    res = {}
+    for pname, prec in (("fp16", ctf.FP16), ("bf16", ctf.BF16)):
+        texs = [ctx.decoder_texture(d, prec) for d in decs]
+        for mname, m in (("list_k4", ctf.method(ctf.LIST, k=4)), ("bilinear4", ctf.method(ctf.BILINEAR4))):
+            fs = ctf.frame_stats_buffer()
+            ctx.filter_layers(uv, duv, texs, mats, m, seed=0, out=out, frame_stats=fs)
+            torch.cuda.synchronize()
+            st = ctf.frame_stats_dict(fs)
+            _, per = timed(lambda: ctx.filter_layers(uv, duv, texs, mats, m, seed=0, out=out), stream,
+                           max(3, args.steps // 2), 2, torch)
+            ms = float(np.mean(per))
+            tflops = st["evals"] * MLP_FLOP / (ms * 1e-3) / 1e12
+            res[f"{pname}_{mname}"] = {
+                "layer_gpixels_per_s": n * npx / (ms * 1e-3) / 1e9, "ms": ms,
+                "texel_evals_per_layer_pixel": st["evals"] / (n * npx),
+                "mfma_tflops": tflops, "mfma_frac": tflops / PEAK_FP16_TFLOPS,
+                "output_hbm_gb_per_s": n * npx * 16 / (ms * 1e-3) / 1e9}
+        for t in texs:
+            t.close()
+    for d in decs:
+        d.close()
+    for pname in ("fp16", "bf16"):
+        res[f"{pname}_speedup_vs_bilinear4"] = (res[f"{pname}_list_k4"]["layer_gpixels_per_s"] /
+                                                res[f"{pname}_bilinear4"]["layer_gpixels_per_s"])
+    return {"workload": f"{args.width}x{args.height} four-plane frame, {n} layers in one launch, "
+                        f"layer l: own 2048^2 procedural texture (seed 11+l) and learned decoder, "
+                        "uv_l = s_l R(theta_l) uv, s_l ~ U[0.25, 4]",
+            "layer_scales": scales, "psnr_db": psnr, "max_abs_fp16_vs_bf16": fp_bf_max,
+            "train_seconds_total": train_s, "runs": res}
 
 
 def main():
@@ -242,6 +345,12 @@ def main():
         "wall_s": {"collaborative": wall_col, "bilinear4": wall_b4},
         "roofline": roof,
     }
+    if not args.no_procedural:
+        log("bench: 1080p procedural texture")
+        res["procedural_1080p"] = bench_procedural(ctx, ctf, cs, torch, args, stream)
+    if not args.no_layers and args.layers > 0:
+        log(f"bench: {args.layers} layers at 4K")
+        res["layers_4k"] = bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
         res["cpu_baseline"] = cpu_baseline(args, sc, dec.params(), l0, l1, H, tex_w, seed_stf)

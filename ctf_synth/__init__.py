@@ -267,16 +267,22 @@ def random_planes_scene(width=1920, height=1080, tex_w=2048, tex_h=2048, seed=1,
     return sc
 
 
-def layer_transform(scene: Scene, seed: int, layer: int):
-    """Per-layer uv: uv_l = R(theta_l) * s_l * uv, derivatives alike.
-
-    s_l ~ U[0.25, 4], theta_l ~ U[0, 2*pi), drawn from (seed, layer).
-    Returns (uv float32, duv float32, s_l, theta_l).
-    """
+def layer_params(seed: int, layer: int):
+    """Scale s_l ~ U[0.25, 4] and rotation theta_l ~ U[0, 2*pi) of material
+    layer ``layer``, drawn from (seed, layer); M_l = s_l R(theta_l)."""
     rng = np.random.default_rng(np.random.SeedSequence([0x1A7, seed, layer]))
     s = rng.uniform(0.25, 4.0)
     th = rng.uniform(0, 2 * math.pi)
     M = s * np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    return s, th, M
+
+
+def layer_transform(scene: Scene, seed: int, layer: int):
+    """Per-layer uv: uv_l = R(theta_l) * s_l * uv, derivatives alike.
+
+    Returns (uv float32, duv float32, s_l, theta_l).
+    """
+    s, th, M = layer_params(seed, layer)
     uv = scene.uv.astype(np.float64) @ M.T
     d = scene.duv.astype(np.float64)
     dx = d[..., 0:2] @ M.T

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libctf_oracle.so")
 
 BILINEAR4, STF1, LIST, BOX, MASK = 0, 1, 2, 3, 4
 FB_STF1, FB_C, FB_CPLUS = 0, 1, 2
+FILTER_BILINEAR, FILTER_BSPLINE, FILTER_CATMULL_ROM = 0, 1, 2
 TEX_SINUSOIDS, TEX_AFFINE, TEX_CONSTANT, TEX_TABLE, TEX_DECODER = 0, 1, 2, 3, 4
 TILE_OK, TILE_CAP, TILE_OVERFLOW, TILE_EMPTY = 1, 2, 4, 8
 MAX_ITEMS = 256
@@ -58,7 +59,8 @@ class Texture(ctypes.Structure):
 class Method(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("box_w", ctypes.c_int32),
                 ("box_h", ctypes.c_int32), ("mask_side", ctypes.c_int32),
-                ("max_evals_per_lane", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+                ("max_evals_per_lane", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("filter", ctypes.c_int32)]
 
 
 TILE_STATS_DTYPE = np.dtype([
@@ -201,8 +203,8 @@ def decoder_texture(tex_w, l0, l1, hidden, params, channels=8):
 # filter
 # ---------------------------------------------------------------------------
 
-def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1) -> Method:
-    return Method(kind, box[0], box[1], mask_side, k, fallback)
+def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_BILINEAR) -> Method:
+    return Method(kind, box[0], box[1], mask_side, k, fallback, filter)
 
 
 def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 8),

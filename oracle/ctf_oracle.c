@@ -127,8 +127,11 @@ int ctfo_texel_eval(const ctfo_texture *tex, const int32_t *xy, int64_t n, doubl
 
 /* ------------------------------------------------------------------------
  * Per-lane footprint (Section 3 and the supplement's code): the float texel
- * position f = uv * dim - 1/2, upper-left texel floor(f), fractional part
- * (s,t), bilinear weights for (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).
+ * position f = uv * dim - 1/2, texel floor(f), fractional part (s,t).
+ * Bilinear uses the 2x2 texels x0..x0+1, y0..y0+1; the bicubic filters of
+ * Section 5 (B-spline, Catmull-Rom) the 4x4 texels x0-1..x0+2, y0-1..y0+2.
+ * (ox, oy) is the footprint's upper-left texel, F its side; tap (i, j) is
+ * texel (ox + i, oy + j) with weight wx[i] wy[j].
  * Minification: a lane is magnifying when both screen-axis footprints span
  * at most one texel (squared lengths <= 1).
  * ---------------------------------------------------------------------- */
@@ -139,11 +142,70 @@ typedef struct {
     int px, py;
     int32_t x0, y0;
     float s, t;
+    int F;                   /* footprint side: 2 or 4 */
+    int32_t ox, oy;          /* upper-left texel of the footprint */
+    float wx[4], wy[4];      /* float32 tap weights (decisions) */
+    double wx64[4], wy64[4]; /* float64 tap weights (colours) */
 } lane_t;
 
 static const float RANGE = 16777216.0f; /* |f| must stay below 2^24 */
 
-static void footprint(const float *uv, const float *duv, int32_t W, int32_t H, lane_t *L)
+/* 1-D tap weights at fractional position x in [0, 1).  Bilinear: (1-x, x).
+ * Uniform cubic B-spline: (1-x)^3/6, (3x^3-6x^2+4)/6, (-3x^3+3x^2+3x+1)/6,
+ * x^3/6.  Catmull-Rom (the cardinal cubic with tangent (f(i+1)-f(i-1))/2):
+ * (-x^3+2x^2-x)/2, (3x^3-5x^2+2)/2, (-3x^3+4x^2+x)/2, (x^3-x^2)/2.
+ * Both cubic sets sum to one; Catmull-Rom has negative weights. */
+static void taps64(int filter, float xs, double w[4])
+{
+    const double x = xs, x2 = x * x, x3 = x2 * x;
+    switch (filter) {
+    case CTFO_FILTER_BSPLINE:
+        w[0] = (1.0 - x) * (1.0 - x) * (1.0 - x) / 6.0;
+        w[1] = (3.0 * x3 - 6.0 * x2 + 4.0) / 6.0;
+        w[2] = (-3.0 * x3 + 3.0 * x2 + 3.0 * x + 1.0) / 6.0;
+        w[3] = x3 / 6.0;
+        break;
+    case CTFO_FILTER_CATMULL_ROM:
+        w[0] = (-x3 + 2.0 * x2 - x) / 2.0;
+        w[1] = (3.0 * x3 - 5.0 * x2 + 2.0) / 2.0;
+        w[2] = (-3.0 * x3 + 4.0 * x2 + x) / 2.0;
+        w[3] = (x3 - x2) / 2.0;
+        break;
+    default:
+        w[0] = 1.0 - x;
+        w[1] = x;
+        w[2] = w[3] = 0.0;
+    }
+}
+
+/* The same weights in float32 with one fixed operation order (products,
+ * then sums left to right, then the constant factor); the stochastic draws
+ * and the fallbacks' discrete choices use these. */
+static void taps32(int filter, float x, float w[4])
+{
+    const float x2 = x * x, x3 = x2 * x, om = 1.0f - x;
+    const float sixth = (float)(1.0 / 6.0);
+    switch (filter) {
+    case CTFO_FILTER_BSPLINE:
+        w[0] = ((om * om) * om) * sixth;
+        w[1] = ((3.0f * x3 - 6.0f * x2) + 4.0f) * sixth;
+        w[2] = (((-3.0f * x3 + 3.0f * x2) + 3.0f * x) + 1.0f) * sixth;
+        w[3] = x3 * sixth;
+        break;
+    case CTFO_FILTER_CATMULL_ROM:
+        w[0] = ((2.0f * x2 - x3) - x) * 0.5f;
+        w[1] = ((3.0f * x3 - 5.0f * x2) + 2.0f) * 0.5f;
+        w[2] = ((-3.0f * x3 + 4.0f * x2) + x) * 0.5f;
+        w[3] = (x3 - x2) * 0.5f;
+        break;
+    default:
+        w[0] = om;
+        w[1] = x;
+        w[2] = w[3] = 0.0f;
+    }
+}
+
+static void footprint(const float *uv, const float *duv, int32_t W, int32_t H, int filter, lane_t *L)
 {
     float u = uv[0], v = uv[1];
     L->active = 0;
@@ -157,20 +219,19 @@ static void footprint(const float *uv, const float *duv, int32_t W, int32_t H, l
     L->y0 = (int32_t)fly;
     L->s = fx - flx;
     L->t = fy - fly;
+    L->F = filter == CTFO_FILTER_BILINEAR ? 2 : 4;
+    L->ox = L->x0 - (L->F == 4);
+    L->oy = L->y0 - (L->F == 4);
+    taps32(filter, L->s, L->wx);
+    taps32(filter, L->t, L->wy);
+    taps64(filter, L->s, L->wx64);
+    taps64(filter, L->t, L->wy64);
     L->active = 1;
     float a = duv[0] * (float)W, b = duv[1] * (float)H;
     float c = duv[2] * (float)W, d = duv[3] * (float)H;
     float rx2 = fmaf(a, a, b * b);
     float ry2 = fmaf(c, c, d * d);
     L->magnify = (rx2 <= 1.0f) && (ry2 <= 1.0f);
-}
-
-static void bilinear_weights(float s, float t, double w[4])
-{
-    w[0] = (1.0 - (double)s) * (1.0 - (double)t);
-    w[1] = (double)s * (1.0 - (double)t);
-    w[2] = (1.0 - (double)s) * (double)t;
-    w[3] = (double)s * (double)t;
 }
 
 /* One-tap STF draw: texel (x0 + [u1 < s], y0 + [u2 < t]) with u1, u2 24-bit
@@ -189,12 +250,33 @@ static void stf_hashes(const lane_t *L, uint64_t seed, int32_t layer, uint32_t h
 
 static float unit24(uint32_t h) { return (float)(h >> 8) * 0x1p-24f; }
 
+/* Cubic one-tap draw along one axis: tap i with probability |w_i| / sum |w|
+ * (the absolute weights, so negative lobes are drawn too).  Partial sums in
+ * float32, left to right; the drawn tap is the number of partial sums at or
+ * below u * sum (a zero-weight tap has an empty interval, never drawn). */
+static int cubic_tap(const float w[4], float u)
+{
+    const float a0 = fabsf(w[0]), a1 = fabsf(w[1]), a2 = fabsf(w[2]), a3 = fabsf(w[3]);
+    const float p1 = a0, p2 = p1 + a1, p3 = p2 + a2, sum = p3 + a3;
+    const float thr = u * sum;
+    return (thr >= p1) + (thr >= p2) + (thr >= p3);
+}
+
+/* One-tap STF draw.  Bilinear: texel (x0 + [u1 < s], y0 + [u2 < t]), i.e.
+ * texel k with probability equal to its weight (to 2^-24).  Bicubic: the
+ * axes are drawn independently by cubic_tap, which picks a tap with
+ * probability |wx_i| |wy_j| / (sum |wx|)(sum |wy|). */
 static void stf_pick(const lane_t *L, uint64_t seed, int32_t layer, int32_t out[2])
 {
     uint32_t h[3];
     stf_hashes(L, seed, layer, h);
-    out[0] = L->x0 + (unit24(h[0]) < L->s ? 1 : 0);
-    out[1] = L->y0 + (unit24(h[1]) < L->t ? 1 : 0);
+    if (L->F == 2) {
+        out[0] = L->x0 + (unit24(h[0]) < L->s ? 1 : 0);
+        out[1] = L->y0 + (unit24(h[1]) < L->t ? 1 : 0);
+    } else {
+        out[0] = L->ox + cubic_tap(L->wx, unit24(h[0]));
+        out[1] = L->oy + cubic_tap(L->wy, unit24(h[1]));
+    }
 }
 
 /* Eq. 2 for a wave of nA participating lanes of which ns produce the
@@ -206,16 +288,6 @@ int ctfo_cplus_target(int32_t nA, int32_t ns, int32_t c)
     const int span = nA - 1 - ns;
     if (span <= 0) return 0;
     return (2 * (nA - 1) * (c - ns) + span) / (2 * span);
-}
-
-/* float32 bilinear weights, for the fallback's discrete choices */
-static void weights32(float s, float t, float w[4])
-{
-    const float is = 1.0f - s, it = 1.0f - t;
-    w[0] = is * it;
-    w[1] = s * it;
-    w[2] = is * t;
-    w[3] = s * t;
 }
 
 static int texel_in(const texel_t *set, int n, int32_t x, int32_t y)
@@ -239,13 +311,14 @@ static int cmp_texel(const void *a, const void *b)
 
 static int unique_set(const lane_t *lanes, int nl, uint64_t A, texel_t *U)
 {
-    texel_t all[4 * MAX_LANES];
+    texel_t all[16 * MAX_LANES];
     int m = 0;
     for (int l = 0; l < nl; ++l) {
         if (!((A >> l) & 1u)) continue;
-        for (int k = 0; k < 4; ++k) {
-            all[m].x = lanes[l].x0 + (k & 1);
-            all[m].y = lanes[l].y0 + (k >> 1);
+        const int F = lanes[l].F;
+        for (int k = 0; k < F * F; ++k) {
+            all[m].x = lanes[l].ox + k % F;
+            all[m].y = lanes[l].oy + k / F;
             ++m;
         }
     }
@@ -290,6 +363,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
     if (!uv || !duv || !tex || !m || !out) return 1;
     if (sw <= 0 || sh <= 0 || tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > MAX_LANES) return 1;
     if (m->max_evals_per_lane < 1 || m->max_evals_per_lane > 4) return 1;
+    if (m->filter < CTFO_FILTER_BILINEAR || m->filter > CTFO_FILTER_CATMULL_ROM) return 1;
     if (m->fallback < CTFO_FB_STF1 || m->fallback > CTFO_FB_CPLUS) return 1;
     const int32_t W = tex->width, H = tex->height;
     const int nl = tile_w * tile_h;
@@ -314,9 +388,9 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 if (xform) {
                     float luv[2], lduv[4];
                     layer_transform(xform, uv + 2 * p, duv + 4 * p, luv, lduv);
-                    footprint(luv, lduv, W, H, L);
+                    footprint(luv, lduv, W, H, m->filter, L);
                 } else {
-                    footprint(uv + 2 * p, duv + 4 * p, W, H, L);
+                    footprint(uv + 2 * p, duv + 4 * p, W, H, m->filter, L);
                 }
                 for (int c = 0; c < 4; ++c) out[4 * p + c] = 0.0;
                 if (stf_xy) stf_xy[2 * p] = stf_xy[2 * p + 1] = INT32_MIN;
@@ -331,18 +405,18 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
         int first = 1;
         for (int l = 0; l < nl; ++l) {
             if (!((A >> l) & 1u)) continue;
-            int64_t x0 = lanes[l].x0, y0 = lanes[l].y0;
+            int64_t x0 = lanes[l].ox, y0 = lanes[l].oy, e = lanes[l].F - 1;
             if (first || x0 < xmin) xmin = x0;
             if (first || y0 < ymin) ymin = y0;
-            if (first || x0 + 1 > xmax) xmax = x0 + 1;
-            if (first || y0 + 1 > ymax) ymax = y0 + 1;
+            if (first || x0 + e > xmax) xmax = x0 + e;
+            if (first || y0 + e > ymax) ymax = y0 + e;
             first = 0;
         }
         const int64_t bbw = nA ? xmax - xmin + 1 : 0;
         const int64_t bbh = nA ? ymax - ymin + 1 : 0;
 
         /* exact unique set (brute force) and 16x16 mask when the box fits */
-        texel_t U[4 * MAX_LANES];
+        texel_t U[16 * MAX_LANES];
         const int nU = unique_set(lanes, nl, A, U);
         uint64_t B[4] = {0, 0, 0, 0};
         const int fits16 = nA && bbw <= 16 && bbh <= 16;
@@ -377,13 +451,15 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             if (side != 16) return 1;
             cap_ok = nA > 0 && bbw <= side && bbh <= side;
             if (cap_ok) {
-                /* each lane of A sets the bits of its 2x2 texels; B is their OR */
+                /* each lane of A sets the bits of its FxF texels; B is their OR */
                 uint64_t Bm[4] = {0, 0, 0, 0};
                 for (int l = 0; l < nl; ++l) {
                     if (!((A >> l) & 1u)) continue;
-                    int t = 16 * (int)(lanes[l].y0 - ymin) + (int)(lanes[l].x0 - xmin);
-                    int ts[4] = {t, t + 1, t + 16, t + 17};
-                    for (int q = 0; q < 4; ++q) Bm[ts[q] >> 6] |= 1ull << (ts[q] & 63);
+                    const int F = lanes[l].F;
+                    for (int q = 0; q < F * F; ++q) {
+                        const int tq = 16 * (int)(lanes[l].oy + q / F - ymin) + (int)(lanes[l].ox + q % F - xmin);
+                        Bm[tq >> 6] |= 1ull << (tq & 63);
+                    }
                 }
                 n = popcount64(Bm[0]) + popcount64(Bm[1]) + popcount64(Bm[2]) + popcount64(Bm[3]);
                 count_ok = n <= (int64_t)k * nA;
@@ -453,15 +529,19 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             for (int c = ns; c < nA; ++c) {           /* spare lanes, Eq. 2 */
                 const int tr = ctfo_cplus_target(nA, ns, c);
                 const lane_t *T = &lanes[rank_lane[tr]];
-                float w[4];
-                weights32(T->s, T->t, w);
-                int cand[4], nc = 0;
+                const int F = T->F;
+                /* candidates: the target's taps (row-major) with a nonzero
+                 * float32 weight that are not in S, drawn by |weight| */
+                float aw[16];
+                int cand[16], nc = 0;
                 float wsum = 0.0f;
-                for (int q = 0; q < 4; ++q) {
-                    const int tq = 16 * (int)(T->y0 + (q >> 1) - ymin) + (int)(T->x0 + (q & 1) - xmin);
-                    if (w[q] > 0.0f && !bit_of(Sm, tq)) {
+                for (int q = 0; q < F * F; ++q) {
+                    const float wq = T->wx[q % F] * T->wy[q / F];
+                    const int tq = 16 * (int)(T->oy + q / F - ymin) + (int)(T->ox + q % F - xmin);
+                    if (wq != 0.0f && !bit_of(Sm, tq)) {
+                        aw[nc] = fabsf(wq);
                         cand[nc++] = q;
-                        wsum += w[q];
+                        wsum += fabsf(wq);
                     }
                 }
                 if (nc == 0) continue;
@@ -471,11 +551,11 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 int pickq = cand[nc - 1];
                 float run = 0.0f;
                 for (int k = 0; k < nc; ++k) {
-                    run += w[cand[k]];
+                    run += aw[k];
                     if (run > thr) { pickq = cand[k]; break; }
                 }
-                prod[nprod].x = T->x0 + (pickq & 1);
-                prod[nprod].y = T->y0 + (pickq >> 1);
+                prod[nprod].x = T->ox + pickq % F;
+                prod[nprod].y = T->oy + pickq / F;
                 ++nprod;
                 ++fb_evals;
             }
@@ -493,23 +573,23 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             if (m->kind == CTFO_BILINEAR4) exact = 1;
             else if (m->kind == CTFO_STF1) exact = 0;
             else exact = ((A >> l) & 1u) && success;
+            const int F = L->F;
             if (!exact && fb != CTFO_FB_STF1 && ((A >> l) & 1u)) {
                 /* Eq. 1 over the produced texels of this footprint with a
                  * nonzero (float32) weight */
-                float w32[4];
-                double w[4], f[4], acc[4] = {0, 0, 0, 0}, sum[4] = {0, 0, 0, 0}, wsum = 0.0;
+                double f[4], acc[4] = {0, 0, 0, 0}, sum[4] = {0, 0, 0, 0}, wsum = 0.0;
                 int N = 0;
-                weights32(L->s, L->t, w32);
-                bilinear_weights(L->s, L->t, w);
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t x = L->x0 + (q & 1), y = L->y0 + (q >> 1);
-                    if (!(w32[q] > 0.0f) || !texel_in(prod, nprod, x, y)) continue;
+                for (int q = 0; q < F * F; ++q) {
+                    const int32_t x = L->ox + q % F, y = L->oy + q / F;
+                    const float w32 = L->wx[q % F] * L->wy[q / F];
+                    const double w = L->wx64[q % F] * L->wy64[q / F];
+                    if (w32 == 0.0f || !texel_in(prod, nprod, x, y)) continue;
                     texel_value(tex, x, y, f);
                     for (int c = 0; c < 4; ++c) {
-                        acc[c] += w[q] * f[c];
+                        acc[c] += w * f[c];
                         sum[c] += f[c];
                     }
-                    wsum += w[q];
+                    wsum += w;
                     ++N;
                 }
                 int32_t pick[2];
@@ -525,13 +605,14 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 continue;
             }
             if (exact) {
-                double w[4], f[4];
-                bilinear_weights(L->s, L->t, w);
-                for (int q = 0; q < 4; ++q) {
-                    texel_value(tex, L->x0 + (q & 1), L->y0 + (q >> 1), f);
-                    for (int c = 0; c < 4; ++c) o[c] += w[q] * f[c];
+                /* the plain definition: every tap of the filter */
+                double f[4];
+                for (int q = 0; q < F * F; ++q) {
+                    const double w = L->wx64[q % F] * L->wy64[q / F];
+                    texel_value(tex, L->ox + q % F, L->oy + q / F, f);
+                    for (int c = 0; c < 4; ++c) o[c] += w * f[c];
                 }
-                if (m->kind == CTFO_BILINEAR4) evals += 4;
+                if (m->kind == CTFO_BILINEAR4) evals += F * F;
             } else {
                 int32_t pick[2];
                 double f[4];

@@ -26,8 +26,10 @@ extern "C" {
 
 enum { CTFO_TEX_SINUSOIDS = 0, CTFO_TEX_AFFINE = 1, CTFO_TEX_CONSTANT = 2,
        CTFO_TEX_TABLE = 3, CTFO_TEX_DECODER = 4 };
+/* CTFO_BILINEAR4 evaluates every tap of the filter (4, or 16 for bicubic) */
 enum { CTFO_BILINEAR4 = 0, CTFO_STF1 = 1, CTFO_LIST = 2, CTFO_BOX = 3, CTFO_MASK = 4 };
 enum { CTFO_FB_STF1 = 0, CTFO_FB_C = 1, CTFO_FB_CPLUS = 2 };
+enum { CTFO_FILTER_BILINEAR = 0, CTFO_FILTER_BSPLINE = 1, CTFO_FILTER_CATMULL_ROM = 2 };
 enum { CTFO_TILE_OK = 1, CTFO_TILE_CAP = 2, CTFO_TILE_OVERFLOW = 4, CTFO_TILE_EMPTY = 8 };
 
 typedef struct ctfo_decoder {
@@ -57,6 +59,7 @@ typedef struct ctfo_method {
     int32_t mask_side;           /* Mask Sampling side (16) */
     int32_t max_evals_per_lane;  /* k >= 1 */
     int32_t fallback;            /* CTFO_FB_* */
+    int32_t filter;              /* CTFO_FILTER_*: 2x2 bilinear or 4x4 bicubic taps */
 } ctfo_method;
 
 /* One record per tile; same field order as the library's tile record. */
