@@ -52,7 +52,7 @@ typedef struct ctf_decoder_s *ctf_decoder;
 
 /* Filtering methods. */
 enum {
-    CTF_BILINEAR4 = 0,  /* exact bilinear, 4 texel evaluations per active pixel */
+    CTF_BILINEAR4 = 0,  /* exact filter, every tap evaluated (4 bilinear, 16 bicubic) per active pixel */
     CTF_STF1 = 1,       /* one-tap STF for every active pixel [Pharr et al. 2024] */
     CTF_LIST = 2,       /* exact duplicate-free set of needed texels (Section 3.1) */
     CTF_BOX = 3,        /* texel bounding box of the wave (Section 3.2) */
@@ -70,6 +70,20 @@ enum {
  *                 among its texels not yet evaluated); then Eq. 1.  Needs
  *                 the wave box to fit 16x16, otherwise CTF_FB_C is used. */
 enum { CTF_FB_STF1 = 0, CTF_FB_C = 1, CTF_FB_CPLUS = 2 };
+
+/* Reconstruction filters (Section 5).  A lane at texel position
+ * f = (u W - 1/2, v H - 1/2), x0 = floor(f.x), s = f.x - x0 (t likewise):
+ *   CTF_FILTER_BILINEAR:    taps x0..x0+1 with weights (1-s, s).
+ *   CTF_FILTER_BSPLINE:     taps x0-1..x0+2, uniform cubic B-spline weights
+ *                           ((1-s)^3, 3s^3-6s^2+4, -3s^3+3s^2+3s+1, s^3) / 6.
+ *   CTF_FILTER_CATMULL_ROM: taps x0-1..x0+2, Catmull-Rom weights
+ *                           (-s^3+2s^2-s, 3s^3-5s^2+2, -3s^3+4s^2+s, s^3-s^2) / 2
+ *                           (negative lobes).
+ * The 2-D weight of tap (i, j) is wx_i wy_j.  The one-tap draw of a cubic
+ * filter picks each axis' tap with probability |w_i| / sum |w| and returns
+ * the texel's value; the fallbacks use the signed weights in Eq. 1 and |w|
+ * for C+'s draws. */
+enum { CTF_FILTER_BILINEAR = 0, CTF_FILTER_BSPLINE = 1, CTF_FILTER_CATMULL_ROM = 2 };
 
 /* Texel producers (Section 3: "produce a texel"). */
 enum {
@@ -149,6 +163,7 @@ typedef struct ctf_method {
     int32_t mask_side;           /* CTF_MASK: 16 */
     int32_t max_evals_per_lane;  /* k in 1..4: a wave succeeds when n <= k * |A| */
     int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
+    int32_t filter;              /* CTF_FILTER_*; the decoder producer takes bilinear only */
 } ctf_method;
 
 /* One record per tile (128 bytes). */

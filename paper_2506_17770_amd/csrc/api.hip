@@ -236,6 +236,8 @@ static ctf_status check_method(const ctf_method* m, const char* who)
     if (m->box_w < 0 || m->box_h < 0) return fail(CTF_ERR_INVALID_ARG, "%s: negative box budget", who);
     if (m->fallback < CTF_FB_STF1 || m->fallback > CTF_FB_CPLUS)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown fallback %d", who, m->fallback);
+    if (m->filter < CTF_FILTER_BILINEAR || m->filter > CTF_FILTER_CATMULL_ROM)
+        return fail(CTF_ERR_INVALID_ARG, "%s: unknown filter %d", who, m->filter);
     return CTF_OK;
 }
 
@@ -256,6 +258,7 @@ static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int
     a.box_h = m->box_h;
     a.max_evals = m->max_evals_per_lane;
     a.fallback = m->fallback;
+    a.filter = m->filter;
     a.seed = seed;
     a.layer = 0;
     a.tile_stats = ts;
@@ -277,6 +280,8 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_d
     if (n_layers < 1 || n_layers > 8) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: n_layers %d", n_layers);
     ctf_status st = check_method(m, "ctf_filter_layers");
     if (st != CTF_OK) return st;
+    if (m->filter != CTF_FILTER_BILINEAR)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the decoder producer takes the bilinear filter only");
     for (int l = 0; l < n_layers; ++l) {
         if (!texs[l] || texs[l]->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: texture %d", l);
         if (texs[l]->dev.kind != CTF_TEX_DECODER || texs[l]->dec.precision != texs[0]->dec.precision)
@@ -305,6 +310,8 @@ ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, 
     ctf_status st = check_method(m, "ctf_filter");
     if (st != CTF_OK) return st;
     if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");
+    if (tex->dev.kind == CTF_TEX_DECODER && m->filter != CTF_FILTER_BILINEAR)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: the decoder producer takes the bilinear filter only");
     DeviceScope ds(ctx->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter: set device");
 

@@ -167,6 +167,88 @@ __device__ __forceinline__ int2 stf_pick(const Footprint& f, uint64_t seed, uint
     return stf_pick_h(f, h1, h2);
 }
 
+// ---------------------------------------------------------------------------
+// reconstruction filters (Section 5): 2x2 bilinear or 4x4 bicubic taps
+// ---------------------------------------------------------------------------
+
+template <int FILTER>
+struct Taps {
+    static constexpr int F = FILTER == CTF_FILTER_BILINEAR ? 2 : 4;  // footprint side
+    static constexpr int O = F == 4 ? 1 : 0;                         // origin = x0 - O
+};
+
+// 1-D tap weights at position x in [0,1), float32, one fixed op order
+// (products, then sums left to right, then the constant factor).
+template <int FILTER>
+__device__ __forceinline__ void taps32(float x, float w[4])
+{
+    const float x2 = x * x, x3 = x2 * x, om = 1.0f - x;
+    if constexpr (FILTER == CTF_FILTER_BSPLINE) {
+        const float sixth = (float)(1.0 / 6.0);
+        w[0] = ((om * om) * om) * sixth;
+        w[1] = ((3.0f * x3 - 6.0f * x2) + 4.0f) * sixth;
+        w[2] = (((-3.0f * x3 + 3.0f * x2) + 3.0f * x) + 1.0f) * sixth;
+        w[3] = x3 * sixth;
+    } else if constexpr (FILTER == CTF_FILTER_CATMULL_ROM) {
+        w[0] = ((2.0f * x2 - x3) - x) * 0.5f;
+        w[1] = ((3.0f * x3 - 5.0f * x2) + 2.0f) * 0.5f;
+        w[2] = ((-3.0f * x3 + 4.0f * x2) + x) * 0.5f;
+        w[3] = (x3 - x2) * 0.5f;
+    } else {
+        w[0] = om;
+        w[1] = x;
+        w[2] = w[3] = 0.0f;
+    }
+}
+
+// Cubic one-tap draw along one axis: tap i with probability |w_i| / sum |w|.
+// The drawn tap is the number of float32 partial sums (left to right) at or
+// below u * sum, so a zero-weight tap is never drawn.
+__device__ __forceinline__ int cubic_tap(const float w[4], float u)
+{
+    const float a0 = __builtin_fabsf(w[0]), a1 = __builtin_fabsf(w[1]);
+    const float a2 = __builtin_fabsf(w[2]), a3 = __builtin_fabsf(w[3]);
+    const float p1 = a0, p2 = p1 + a1, p3 = p2 + a2, sum = p3 + a3;
+    const float thr = u * sum;
+    return (thr >= p1) + (thr >= p2) + (thr >= p3);
+}
+
+// One-tap draw for any filter (bilinear: stf_pick_h).
+template <int FILTER>
+__device__ __forceinline__ int2 stf_pick_filter(const Footprint& f, uint32_t h1, uint32_t h2)
+{
+    if constexpr (FILTER == CTF_FILTER_BILINEAR) {
+        return stf_pick_h(f, h1, h2);
+    } else {
+        float wx[4], wy[4];
+        taps32<FILTER>(f.s, wx);
+        taps32<FILTER>(f.t, wy);
+        return make_int2(f.x0 - 1 + cubic_tap(wx, (float)(h1 >> 8) * 0x1p-24f),
+                         f.y0 - 1 + cubic_tap(wy, (float)(h2 >> 8) * 0x1p-24f));
+    }
+}
+
+// Exact cubic filtering of 16 texels v[4j + i] (tap (i, j)): each row as a
+// fused chain in x, then the rows in y.  One fixed op sequence for every
+// method, like bilerp for the 2x2 case.
+__device__ __forceinline__ float4 row4(const float wx[4], float4 a, float4 b, float4 c, float4 d)
+{
+    float4 r;
+    r.x = __builtin_fmaf(wx[3], d.x, __builtin_fmaf(wx[2], c.x, __builtin_fmaf(wx[1], b.x, wx[0] * a.x)));
+    r.y = __builtin_fmaf(wx[3], d.y, __builtin_fmaf(wx[2], c.y, __builtin_fmaf(wx[1], b.y, wx[0] * a.y)));
+    r.z = __builtin_fmaf(wx[3], d.z, __builtin_fmaf(wx[2], c.z, __builtin_fmaf(wx[1], b.z, wx[0] * a.z)));
+    r.w = __builtin_fmaf(wx[3], d.w, __builtin_fmaf(wx[2], c.w, __builtin_fmaf(wx[1], b.w, wx[0] * a.w)));
+    return r;
+}
+
+// accumulate row j (weight wyj) into acc: j == 0 starts the chain
+__device__ __forceinline__ float4 col_acc(float wyj, float4 r, float4 acc, bool first)
+{
+    if (first) return make_float4(wyj * r.x, wyj * r.y, wyj * r.z, wyj * r.w);
+    return make_float4(__builtin_fmaf(wyj, r.x, acc.x), __builtin_fmaf(wyj, r.y, acc.y),
+                       __builtin_fmaf(wyj, r.z, acc.z), __builtin_fmaf(wyj, r.w, acc.w));
+}
+
 // 256-bit footprint mask from the mask of footprint corners:
 // B = C | C<<1 | C<<16 | C<<17 (words low first; wave-uniform, scalar ops).
 __device__ __forceinline__ void footprint_mask(const uint64_t C[4], uint64_t B[4])
@@ -177,6 +259,54 @@ __device__ __forceinline__ void footprint_mask(const uint64_t C[4], uint64_t B[4
         B[w] = C[w] | (C[w] << 1) | (lo >> 63) | (C[w] << 16) | (lo >> 48) | (C[w] << 17) | (lo >> 47);
     }
 }
+
+// The same for FxF footprints: B = OR over 0 <= dx, dy < F of C << (16 dy + dx)
+// (corners of a box inside 16x16 have dx <= 16 - F, so no row wraps).
+template <int F>
+__device__ __forceinline__ void footprint_mask_f(const uint64_t C[4], uint64_t B[4])
+{
+    if constexpr (F == 2) {
+        footprint_mask(C, B);
+    } else {
+        uint64_t Hm[4];   // the row spread: C | C<<1 | C<<2 | C<<3
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t lo = w > 0 ? C[w - 1] : 0ull;
+            Hm[w] = C[w] | (C[w] << 1) | (lo >> 63) | (C[w] << 2) | (lo >> 62) | (C[w] << 3) | (lo >> 61);
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t lo = w > 0 ? Hm[w - 1] : 0ull;
+            B[w] = Hm[w] | (Hm[w] << 16) | (lo >> 48) | (Hm[w] << 32) | (lo >> 32) | (Hm[w] << 48) | (lo >> 16);
+        }
+    }
+}
+
+// A wave's walk over tiles t0, t0 + step, ... of a row-major tile grid,
+// keeping (tx, ty) up to date with scalar adds: one division per wave
+// instead of a 64-bit division per tile.
+struct TileWalk {
+    int64_t tile;
+    int tx, ty;
+    int dtx, dty, tiles_x;
+    __device__ __forceinline__ TileWalk(int64_t t0, int64_t step, int tiles_x_) : tile(t0), tiles_x(tiles_x_)
+    {
+        tx = (int)(t0 % tiles_x_);
+        ty = (int)(t0 / tiles_x_);
+        dtx = (int)(step % tiles_x_);
+        dty = (int)(step / tiles_x_);
+    }
+    __device__ __forceinline__ void advance(int64_t step)
+    {
+        tile += step;
+        tx += dtx;
+        ty += dty;
+        if (tx >= tiles_x) {
+            tx -= tiles_x;
+            ++ty;
+        }
+    }
+};
 
 // Frame totals of one wave over all its tiles, added to the frame record
 // once at the end (one set of atomics per wave).

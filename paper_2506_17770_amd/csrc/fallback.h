@@ -8,9 +8,10 @@
 //       once, by the lanes of rank 0..|S|-1 in A; each remaining lane of
 //       rank c adds a texel of the footprint of the lane of rank
 //       round((|A|-1)(c-|S|)/(|A|-1-|S|)) (Eq. 2), drawn with probability
-//       proportional to its float32 weight among that footprint's texels
-//       not in S (the last such texel if the running sum never passes the
-//       threshold); a lane whose target has no such texel produces nothing.
+//       proportional to the absolute value of its float32 weight among that
+//       footprint's nonzero-weight texels not in S (the last such texel if
+//       the running sum never passes the threshold); a lane whose target
+//       has no such texel produces nothing.
 //       C+ needs the wave box to fit the 16x16 mask; otherwise C is used.
 // Each lane of A then weights the produced texels of its footprint that
 // have a nonzero float32 weight with Eq. 1.
@@ -34,15 +35,6 @@ __device__ __forceinline__ int cplus_target(int nA, int ns, int c)
     return span <= 0 ? 0 : (2 * (nA - 1) * (c - ns) + span) / (2 * span);
 }
 
-__device__ __forceinline__ void weights32(float s, float t, float w[4])
-{
-    const float is = 1.0f - s, it = 1.0f - t;
-    w[0] = is * it;
-    w[1] = s * it;
-    w[2] = is * t;
-    w[3] = s * t;
-}
-
 struct FallbackPlan {
     bool produces;   // this lane evaluates a texel
     int2 texel;      // ... this one
@@ -60,7 +52,7 @@ struct StashEntry {  // a lane's footprint, read by the spare lanes of C+
 // C+ falls back to C when the box exceeds 16x16.  LDS is the kernel's
 // per-wave struct; its members keys (>= 2 KB), rank and bytes (256 bytes
 // each) are overwritten.  h3 is this lane's third hash of the draw chain.
-template <class LDS>
+template <int FILTER, class LDS>
 __device__ FallbackPlan plan_fallback(LDS& L, int fb, bool inA, int nA, int rankA, const Footprint& f, int2 pick,
                                       uint32_t h3, bool fits16, int xmin, int ymin)
 {
@@ -97,31 +89,38 @@ __device__ FallbackPlan plan_fallback(LDS& L, int fb, bool inA, int nA, int rank
             P.produces = true;
             P.texel = make_int2(xmin + (t & 15), ymin + (t >> 4));
         } else if (inA) {
+            constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
             const StashEntry T = stash[L.bytes[cplus_target(nA, ns, rankA)]];
-            float w[4];
-            weights32(T.s, T.t, w);
+            float wx[4], wy[4];
+            taps32<FILTER>(T.s, wx);
+            taps32<FILTER>(T.t, wy);
+            const int ox = T.x0 - O, oy = T.y0 - O;
+            // candidates: taps (row-major) with a nonzero weight, not in S
+            uint32_t cand = 0u;
             float wsum = 0.f;
-            bool cand[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int tq = 16 * (T.y0 + (q >> 1) - ymin) + (T.x0 + (q & 1) - xmin);
-                cand[q] = w[q] > 0.0f && !((S[tq >> 6] >> (tq & 63)) & 1u);
-                if (cand[q]) wsum += w[q];
+            for (int q = 0; q < F * F; ++q) {
+                const float wq = wx[q % F] * wy[q / F];
+                const int tq = 16 * (oy + q / F - ymin) + (ox + q % F - xmin);
+                if (wq != 0.0f && !((S[tq >> 6] >> (tq & 63)) & 1u)) {
+                    cand |= 1u << q;
+                    wsum += __builtin_fabsf(wq);
+                }
             }
-            if (wsum > 0.0f) {
+            if (cand) {
                 const float thr = (float)(h3 >> 8) * 0x1p-24f * wsum;
                 float run = 0.f;
                 int pq = -1;
                 bool done = false;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!cand[q] || done) continue;
+                for (int q = 0; q < F * F; ++q) {
+                    if (!((cand >> q) & 1u) || done) continue;
                     pq = q;
-                    run += w[q];
+                    run += __builtin_fabsf(wx[q % F] * wy[q / F]);
                     done = run > thr;
                 }
                 P.produces = true;
-                P.texel = make_int2(T.x0 + (pq & 1), T.y0 + (pq >> 1));
+                P.texel = make_int2(ox + pq % F, oy + pq / F);
             }
         }
     }
@@ -140,23 +139,26 @@ __device__ FallbackPlan plan_fallback(LDS& L, int fb, bool inA, int nA, int rank
 }
 
 // Eq. 1 for a lane of A, once the produced values are in vals[0..nprod):
-// the produced texels of its footprint with a nonzero float32 weight,
-// weighted, plus their mean times the weight of the missing texels.  If no
-// texel qualifies (the drawn texel's weight underflowed to zero) the drawn
-// texel's value is returned.
-template <class LDS>
+// among its footprint's FxF taps (signed float32 weights wx_i wy_j), the
+// produced texels with a nonzero weight, weighted, plus their mean times the
+// weight of the missing texels.  If no texel qualifies (the drawn texel's
+// weight underflowed to zero) the drawn texel's value is returned.
+template <int FILTER, class LDS>
 __device__ float4 fallback_color(const LDS& L, const FallbackPlan& P, const Footprint& f, int2 pick, int xmin,
                                  int ymin)
 {
+    constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
     const int2* produced = reinterpret_cast<const int2*>(L.keys);
-    float w[4];
-    weights32(f.s, f.t, w);
+    float wx[4], wy[4];
+    taps32<FILTER>(f.s, wx);
+    taps32<FILTER>(f.t, wy);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), sum = acc;
     float wsum = 0.f;
     int N = 0, own = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int x = f.x0 + (q & 1), y = f.y0 + (q >> 1);
+    for (int q = 0; q < F * F; ++q) {
+        const int x = f.x0 - O + q % F, y = f.y0 - O + q / F;
+        const float wq = wx[q % F] * wy[q / F];
         int slot = -1;
         if (P.table) {
             slot = (int)L.rank[16 * (y - ymin) + (x - xmin)] - 1;
@@ -170,17 +172,17 @@ __device__ float4 fallback_color(const LDS& L, const FallbackPlan& P, const Foot
             }
         }
         if (x == pick.x && y == pick.y) own = slot;
-        if (slot < 0 || !(w[q] > 0.0f)) continue;
+        if (slot < 0 || wq == 0.0f) continue;
         const float4 v = L.vals[slot];
-        acc.x = __builtin_fmaf(w[q], v.x, acc.x);
-        acc.y = __builtin_fmaf(w[q], v.y, acc.y);
-        acc.z = __builtin_fmaf(w[q], v.z, acc.z);
-        acc.w = __builtin_fmaf(w[q], v.w, acc.w);
+        acc.x = __builtin_fmaf(wq, v.x, acc.x);
+        acc.y = __builtin_fmaf(wq, v.y, acc.y);
+        acc.z = __builtin_fmaf(wq, v.z, acc.z);
+        acc.w = __builtin_fmaf(wq, v.w, acc.w);
         sum.x += v.x;
         sum.y += v.y;
         sum.z += v.z;
         sum.w += v.w;
-        wsum += w[q];
+        wsum += wq;
         ++N;
     }
     if (N == 0) return L.vals[own];

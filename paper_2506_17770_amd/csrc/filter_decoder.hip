@@ -133,12 +133,11 @@ __device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& 
 // layer's planes.
 template <int METHOD, int P, bool STATS, bool FB>
 __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& G, const FwdWeights<P>& W,
-                                         const Biases& Bz, DecLds& L, int64_t tile, const Footprint& f,
-                                         FrameCounters& fc)
+                                         const Biases& Bz, DecLds& L, int64_t tile, int tx, int ty,
+                                         const Footprint& f, FrameCounters& fc)
 {
     const int lane = lane_id();
     const int j = lane & 15, g = lane >> 4;
-    const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
     const bool in_screen = px < a.sw && py < a.sh;
     const int64_t pix = (int64_t)py * a.sw + px;
@@ -245,7 +244,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
             for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
         }
     } else if (fallback) {
-        fp = plan_fallback(L, a.fallback, inA, nA, mbcnt(A), f, pick, pcg_hash(h2), fits16, xmin, ymin);
+        fp = plan_fallback<CTF_FILTER_BILINEAR>(L, a.fallback, inA, nA, mbcnt(A), f, pick, pcg_hash(h2), fits16, xmin, ymin);
         R = fp.nprod + popc64(mdraw);
         if (fp.produces) L.rows[fp.slot] = fp.texel;
         if (draws && !inA) L.rows[fp.nprod + mbcnt(mdraw)] = pick;
@@ -282,9 +281,34 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
                     base += popc64(B[w]);
                 }
             }
+            if (sorted && inA) {
+                // List past 16x16: the lane's four item indices by binary
+                // search, kept in the (otherwise unused) rank table
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
+                                         (uint32_t)(f.x0 + (q & 1) - xmin);
+                    L.rank[4 * lane + q] = (uint8_t)dec_list_find(L, n, key);
+                }
+            }
         }
         if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
     }
+    // the debug draws are known now; write them before the decode so the
+    // draw is not kept live across it
+    if (in_screen && a.stf_xy)
+        reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+    // where this lane's four texels sit: item indices gi + {0, 1, gd, gd + 1}
+    // (Box: directly; Mask and List: through the rank table)
+    int gi = 0, gd = 0;
+    if constexpr (METHOD == CTF_BOX) {
+        gi = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
+        gd = bbw;
+    } else if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
+        gi = sorted ? 4 * lane : 16 * (f.y0 - ymin) + (f.x0 - xmin);
+        gd = sorted ? 2 : 16;
+    }
+    const int draw_row = ns + mbcnt(stfmask);
     wave_lds_sync();
 
     // ---- decode the rows, 16 per MFMA tile; the latent gathers of the
@@ -292,29 +316,11 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
     decode_rows<P>(L, R, G, W, Bz, j, g);
     wave_lds_sync();
 
-    int idx[4] = {0, 0, 0, 0};
-    if constexpr (kCollab) {
+    int idx[4] = {gi, gi + 1, gi + gd, gi + gd + 1};
+    if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
         if (exact) {
-            if constexpr (METHOD == CTF_BOX) {
-                const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
-                idx[0] = b;
-                idx[1] = b + 1;
-                idx[2] = b + bbw;
-                idx[3] = b + bbw + 1;
-            } else if (sorted) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                         (uint32_t)(f.x0 + (q & 1) - xmin);
-                    idx[q] = dec_list_find(L, n, key);
-                }
-            } else {
-                const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                idx[0] = L.rank[t];
-                idx[1] = L.rank[t + 1];
-                idx[2] = L.rank[t + 16];
-                idx[3] = L.rank[t + 17];
-            }
+            for (int q = 0; q < 4; ++q) idx[q] = L.rank[idx[q]];
         }
     }
 
@@ -327,17 +333,13 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
         }
     } else if (fallback) {
         if (draws && !inA) res = L.vals[fp.nprod + mbcnt(mdraw)];
-        if (inA) res = fallback_color(L, fp, f, pick, xmin, ymin);
+        if (inA) res = fallback_color<CTF_FILTER_BILINEAR>(L, fp, f, pick, xmin, ymin);
     } else {
-        if (draws) res = L.vals[ns + mbcnt(stfmask)];
+        if (draws) res = L.vals[draw_row];
         if (kCollab && exact)
             res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]], L.vals[idx[3]]);
     }
-    if (in_screen) {
-        reinterpret_cast<float4*>(a.out)[pix] = res;
-        if (a.stf_xy)
-            reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
-    }
+    if (in_screen) reinterpret_cast<float4*>(a.out)[pix] = res;
     if (lane == 0) {
         if (a.tile_stats) {
             ctf_tile_stats S;
@@ -364,13 +366,14 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
 }
 
 // Inputs of a tile for this lane, NaN (inactive) outside the band or screen.
-__device__ __forceinline__ void load_tile_px(const FilterArgs& a, int64_t t, int64_t band_e, float2& uv, float4& d)
+__device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
+                                             float4& d)
 {
     const int lane = lane_id();
     uv = make_float2(__builtin_nanf(""), 0.f);
     d = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t >= band_e) return;
-    const int px = (int)(t % a.tiles_x) * kTile + (lane & 7), py = (int)(t / a.tiles_x) * kTile + (lane >> 3);
+    if (t.tile >= band_e) return;
+    const int px = t.tx * kTile + (lane & 7), py = t.ty * kTile + (lane >> 3);
     if (px < a.sw && py < a.sh) {
         const int64_t q = (int64_t)py * a.sw + px;
         uv = reinterpret_cast<const float2*>(a.uv)[q];
@@ -393,8 +396,15 @@ struct Band {
     }
 };
 
+// Waves per SIMD the register budget of the single-layer kernel is sized
+// for: the collaborative methods need the bound of three to fit in 168
+// registers; the others fit three anyway and keep the compiler's schedule.
+template <int METHOD>
+constexpr int dec_waves_per_simd() { return METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK ? 3 : 2; }
+
 template <int METHOD, int P, bool STATS, bool FB>
-__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, DevDecoderWeights D)
+__global__ __launch_bounds__(64 * kDecWaves, dec_waves_per_simd<METHOD>()) void k_filter_dec(FilterArgs a,
+                                                                                             DevDecoderWeights D)
 {
     __shared__ DecLds lds_all[kDecWaves];
     const int wid = threadIdx.x >> 6;
@@ -411,13 +421,16 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_dec(FilterArgs a, 
     // the inputs of the wave's next tile are loaded one tile ahead
     float2 uv_next;
     float4 d_next;
-    load_tile_px(a, band.begin + band.lw, band.end, uv_next, d_next);
-    for (int64_t tile = band.begin + band.lw; tile < band.end; tile += band.nw) {
+    TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+    load_tile_px(a, next, band.end, uv_next, d_next);
+    while (next.tile < band.end) {
+        const TileWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
-        load_tile_px(a, tile + band.nw, band.end, uv_next, d_next);
+        next.advance(band.nw);
+        load_tile_px(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
-        dec_tile<METHOD, P, STATS, FB>(a, D.grid, W, Bz, L, tile, f, fc);
+        dec_tile<METHOD, P, STATS, FB>(a, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
@@ -460,17 +473,20 @@ __global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_layers(FilterArgs 
         al.layer = (uint32_t)l;
         float2 uv_next;
         float4 d_next;
-        load_tile_px(a, band.begin + band.lw, band.end, uv_next, d_next);
-        for (int64_t tile = band.begin + band.lw; tile < band.end; tile += band.nw) {
+        TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+        load_tile_px(a, next, band.end, uv_next, d_next);
+        while (next.tile < band.end) {
+            const TileWalk cur = next;
             const float2 uv = uv_next;
             const float4 d = d_next;
-            load_tile_px(a, tile + band.nw, band.end, uv_next, d_next);
+            next.advance(band.nw);
+            load_tile_px(a, next, band.end, uv_next, d_next);
             // layer coordinates, float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u)
             const float lu = __builtin_fmaf(m01, uv.y, m00 * uv.x), lv = __builtin_fmaf(m11, uv.y, m10 * uv.x);
             const float4 ld = make_float4(__builtin_fmaf(m01, d.y, m00 * d.x), __builtin_fmaf(m11, d.y, m10 * d.x),
                                           __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
             const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
-            dec_tile<METHOD, P, STATS, FB>(al, D.grid, W, Bz, L, tile, f, fc);
+            dec_tile<METHOD, P, STATS, FB>(al, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
         }
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);

@@ -1,359 +1,11 @@
-// filter_simt.hip -- collaborative filtering with per-lane texel production.
-//
-// One 8x8 tile per wave64, four waves per workgroup.  Each lane produces at
-// most k texels per wave (k = max_evals_per_lane); the produced values are
-// staged in the wave's LDS slice and gathered by item index.  Used for the
-// procedural, stored-table and test texel producers (the decoder producer
-// batches its texels into MFMA tiles instead, see filter_decoder.hip).
-//
-// Paper: Section 3 (three-step flow), 3.1 List Merge, 3.2 Box Sampling,
-// 3.3 Mask Sampling (bijection h of Figure 3), supplement Section 2 (edge
-// remapping: item i is produced by lane h(i, A)), Section 3.4 (fallbacks:
-// one-tap STF, C of Eq. 1 and C+ of Eq. 2, fallback.h).
-#include "ctf_device.h"
-#include "ctf_internal.h"
-#include "fallback.h"
+// filter_simt.hip -- per-lane filter kernels for the bilinear filter, the
+// filter dispatcher and raw texel evaluation (kernels in filter_simt.h; the
+// bicubic instantiations are compiled in filter_simt_cubic.hip).
+#include "filter_simt.h"
 
 namespace ctf {
 
 namespace {
-
-constexpr int kWavesPerBlock = 4;
-
-struct WaveLds {
-    float4 vals[kMaxItems];     // produced texel values, by item index
-    uint64_t keys[kMaxItems];   // List: sorted unique texel keys (dy << 32 | dx)
-    uint16_t items[kMaxItems];  // Mask: item i -> mask position t = h(i, B)
-    uint8_t rank[256];          // Mask: position t -> item index h^-1(t, B)
-    uint8_t bytes[256];         // Mask: footprint-corner scatter before the ballots
-};
-
-// Exact set of the wave's texels as sorted unique keys (any box size): a
-// bitonic sort of the 4|A| footprint keys in LDS, then compaction of the
-// first key of every run.  Returns n = |U|; keys[0..n) hold U in (y, x)
-// order.
-__device__ int list_unique_sorted(WaveLds& L, bool inA, const Footprint& f, int xmin, int ymin)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint64_t key = ~0ull;
-        if (inA) {
-            const uint32_t dx = (uint32_t)(f.x0 + (q & 1) - xmin);
-            const uint32_t dy = (uint32_t)(f.y0 + (q >> 1) - ymin);
-            key = ((uint64_t)dy << 32) | dx;
-        }
-        L.keys[4 * lane + q] = key;
-    }
-    for (int size = 2; size <= kMaxItems; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            wave_lds_sync();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int p = lane + kWave * h;                 // pair index 0..127
-                const int i = (p / stride) * stride * 2 + (p % stride);
-                const int j = i + stride;
-                const bool up = (i & size) == 0;
-                const uint64_t a = L.keys[i], b = L.keys[j];
-                if ((a > b) == up) {
-                    L.keys[i] = b;
-                    L.keys[j] = a;
-                }
-            }
-        }
-    }
-    wave_lds_sync();
-    uint64_t k4[4];
-    bool first[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int i = kWave * c + lane;
-        k4[c] = L.keys[i];
-        first[c] = k4[c] != ~0ull && (i == 0 || L.keys[i - 1] != k4[c]);
-    }
-    wave_lds_sync();
-    int base = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint64_t b = ballot(first[c]);
-        if (first[c]) L.keys[base + mbcnt(b)] = k4[c];
-        base += popc64(b);
-    }
-    wave_lds_sync();
-    return base;
-}
-
-__device__ __forceinline__ int list_find(const WaveLds& L, int n, uint64_t key)
-{
-    int lo = 0, hi = n;  // first index with keys[idx] >= key
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (L.keys[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-template <int METHOD, int TEX, bool STATS>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterArgs a, DevTexture T)
-{
-    __shared__ WaveLds lds_all[kWavesPerBlock];
-    const int wid = threadIdx.x / kWave;
-    const int lane = lane_id();
-    WaveLds& L = lds_all[wid];
-    FrameCounters fc;
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wid; tile < a.ntiles; tile += nw) {
-        const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
-        const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-        const bool in_screen = px < a.sw && py < a.sh;
-        const int64_t pix = (int64_t)py * a.sw + px;
-
-        // ---- step 1: footprint, participation (A = active and magnifying)
-        Footprint f;
-        {
-            float2 uv = make_float2(__builtin_nanf(""), 0.f);
-            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (in_screen) {
-                uv = reinterpret_cast<const float2*>(a.uv)[pix];
-                d = reinterpret_cast<const float4*>(a.duv)[pix];
-            }
-            f = footprint(uv.x, uv.y, d, (float)T.width, (float)T.height);
-        }
-        const bool inA = f.active && f.magnify;
-        const uint64_t act = ballot(f.active);
-        const uint64_t A = ballot(inA);
-        const int nA = popc64(A);
-        const int rankA = mbcnt(A);  // edge remapping: lane of rank r produces items r, r+|A|, ...
-
-        // ---- step 2: wave texel box over A
-        int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
-        constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
-        if (kCollab || STATS) {
-            if (nA > 0) {
-                xmin = wave_min(inA ? f.x0 : INT32_MAX);
-                ymin = wave_min(inA ? f.y0 : INT32_MAX);
-                bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
-                bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
-            }
-        }
-        const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
-
-        // ---- 16x16 wave mask B (Mask Sampling; also the exact set when it fits)
-        uint64_t B[4] = {0, 0, 0, 0};
-        int nmask = 0;
-        constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
-        if (kNeedMask && fits16) {
-            // corners of the footprints (mask C) by one LDS byte per lane and
-            // four ballots; B = C | C<<1 | C<<16 | C<<17
-            reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
-            wave_lds_sync();
-            if (inA) L.bytes[16 * (f.y0 - ymin) + (f.x0 - xmin)] = 1;
-            wave_lds_sync();
-            uint64_t C[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) C[w] = ballot(L.bytes[64 * w + lane] != 0);
-            footprint_mask(C, B);
-            // h and h^-1 as tables: set bit t of rank r gives items[r] = t, rank[t] = r
-            int base = 0;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                if ((B[w] >> lane) & 1u) {
-                    const int r = base + mbcnt(B[w]);
-                    L.items[r] = (uint16_t)(64 * w + lane);
-                    L.rank[64 * w + lane] = (uint8_t)r;
-                }
-                base += popc64(B[w]);
-            }
-            nmask = base;
-            wave_lds_sync();
-        }
-
-        // ---- step 3: the method's decision
-        const int k = a.max_evals;
-        int n = 0;
-        bool cap_ok = true, count_ok = true, success = false, sorted = false;
-        int unique = nmask;
-        if constexpr (METHOD == CTF_BOX) {
-            // area in 64 bits: sides can be large when A spans several surfaces
-            const int64_t area = (int64_t)bbw * bbh;
-            n = area > INT32_MAX ? INT32_MAX : (int)area;
-            cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
-            count_ok = area <= (int64_t)k * nA;
-            success = nA > 0 && cap_ok && count_ok;
-        } else if constexpr (METHOD == CTF_MASK) {
-            cap_ok = fits16;
-            n = fits16 ? nmask : 0;
-            count_ok = n <= k * nA;
-            success = fits16 && count_ok;
-        } else if constexpr (METHOD == CTF_LIST) {
-            if (nA > 0 && !fits16) {
-                n = list_unique_sorted(L, inA, f, xmin, ymin);
-                sorted = true;
-            } else {
-                n = nmask;
-            }
-            unique = n;
-            count_ok = n <= k * nA;
-            success = nA > 0 && count_ok;
-        }
-        if constexpr (STATS && METHOD != CTF_LIST) {
-            if (nA > 0 && !fits16) unique = list_unique_sorted(L, inA, f, xmin, ymin);
-        }
-        if (nA == 0) unique = 0;
-
-        // lanes whose output is exact bilinear vs a one-tap draw
-        bool exact, draws;
-        if constexpr (METHOD == CTF_BILINEAR4) {
-            exact = f.active;
-            draws = false;
-        } else if constexpr (METHOD == CTF_STF1) {
-            exact = false;
-            draws = f.active;
-        } else {
-            exact = inA && success;
-            draws = f.active && !exact;
-        }
-        const uint64_t stfmask = ballot(draws);
-
-        // ---- texel production: each lane evaluates at most one texel per round
-        float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
-        int2 pick = make_int2(INT32_MIN, INT32_MIN);
-        uint32_t h1 = 0, h2 = 0;
-        if (draws) {
-            stf_hashes(a.seed, a.layer, px, py, h1, h2);
-            pick = stf_pick_h(f, h1, h2);
-        }
-        // fallback C / C+ for the lanes of A of a failed wave
-        const bool fallback = kCollab && !success && nA > 0 && a.fallback != CTF_FB_STF1;
-        FallbackPlan P{};
-        if (fallback) P = plan_fallback(L, a.fallback, inA, nA, rankA, f, pick, pcg_hash(h2), fits16, xmin, ymin);
-
-        if constexpr (METHOD == CTF_BILINEAR4) {
-            if (exact) {
-                const float4 v0 = texel_eval<TEX>(T, f.x0, f.y0);
-                const float4 v1 = texel_eval<TEX>(T, f.x0 + 1, f.y0);
-                const float4 v2 = texel_eval<TEX>(T, f.x0, f.y0 + 1);
-                const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
-                res = bilerp(f.s, f.t, v0, v1, v2, v3);
-            }
-        } else if (fallback) {
-            // lanes of A evaluate the planned texels; minifying lanes draw
-            const bool pa = inA && P.produces, pd = draws && !inA;
-            if (pa || pd) {
-                const int2 e = pa ? P.texel : pick;
-                const float4 v = texel_eval<TEX>(T, e.x, e.y);
-                if (pa) L.vals[P.slot] = v;
-                else res = v;
-            }
-            wave_lds_sync();
-            if (inA) res = fallback_color(L, P, f, pick, xmin, ymin);
-        } else {
-            for (int round = 0; round < (kCollab ? k : 1); ++round) {
-                const int item = rankA + round * nA;
-                const bool produce = kCollab && success && inA && item < n;
-                const bool draw_now = draws && round == 0;
-                if (ballot(produce || draw_now) == 0) break;
-                int ex = pick.x, ey = pick.y;
-                if (produce) {
-                    if constexpr (METHOD == CTF_BOX) {
-                        ex = xmin + item % bbw;
-                        ey = ymin + item / bbw;
-                    } else {
-                        if (sorted) {
-                            const uint64_t key = L.keys[item];
-                            ex = xmin + (int)(uint32_t)key;
-                            ey = ymin + (int)(key >> 32);
-                        } else {
-                            const int t = L.items[item];
-                            ex = xmin + (t & 15);
-                            ey = ymin + (t >> 4);
-                        }
-                    }
-                    if (a.lists) {
-                        int32_t* e = a.lists + ((size_t)tile * kMaxItems + item) * 2;
-                        e[0] = ex;
-                        e[1] = ey;
-                    }
-                }
-                if (produce || draw_now) {
-                    const float4 v = texel_eval<TEX>(T, ex, ey);
-                    if (produce) L.vals[item] = v;
-                    if (draw_now) res = v;
-                }
-            }
-            if constexpr (kCollab) {
-                // ---- gather: item index of each footprint texel, then weight
-                wave_lds_sync();
-                if (exact) {
-                    int idx[4];
-                    if constexpr (METHOD == CTF_BOX) {
-                        const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
-                        idx[0] = b;
-                        idx[1] = b + 1;
-                        idx[2] = b + bbw;
-                        idx[3] = b + bbw + 1;
-                    } else {
-                        if (sorted) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const uint64_t key =
-                                    ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                    (uint32_t)(f.x0 + (q & 1) - xmin);
-                                idx[q] = list_find(L, n, key);
-                            }
-                        } else {
-                            const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                            idx[0] = L.rank[t];
-                            idx[1] = L.rank[t + 1];
-                            idx[2] = L.rank[t + 16];
-                            idx[3] = L.rank[t + 17];
-                        }
-                    }
-                    res = bilerp(f.s, f.t, L.vals[idx[0]], L.vals[idx[1]], L.vals[idx[2]],
-                                 L.vals[idx[3]]);
-                }
-            }
-        }
-
-        // ---- outputs
-        if (in_screen) {
-            reinterpret_cast<float4*>(a.out)[pix] = res;
-            if (a.stf_xy) reinterpret_cast<int2*>(a.stf_xy)[pix] =
-                draws ? pick : make_int2(INT32_MIN, INT32_MIN);
-        }
-        const int nstf = popc64(stfmask);
-        int evals;
-        if constexpr (METHOD == CTF_BILINEAR4) evals = 4 * popc64(act);
-        else if (fallback) evals = P.nprod + popc64(stfmask & ~A);
-        else evals = (success ? n : 0) + nstf;
-
-        if (lane == 0) {
-            if (a.tile_stats) {
-                ctf_tile_stats S;
-                S.active = act;
-                S.part = A;
-                S.stf = stfmask;
-                for (int w = 0; w < 4; ++w) S.mask[w] = fits16 ? B[w] : 0ull;
-                S.xmin = xmin;
-                S.ymin = ymin;
-                S.bbw = bbw;
-                S.bbh = bbh;
-                S.n = n;
-                S.unique = unique;
-                S.evals = evals;
-                S.flags = (success ? CTF_TILE_OK : 0) | (nA && !cap_ok ? CTF_TILE_CAP : 0) |
-                          (nA && cap_ok && !count_ok ? CTF_TILE_OVERFLOW : 0) |
-                          (nA == 0 ? CTF_TILE_EMPTY : 0);
-                for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
-                a.tile_stats[tile] = S;
-            }
-        }
-        if (act) fc.add(evals, popc64(act), nstf, popc64(act & ~A), 0, kCollab && success, kCollab && nA && !success);
-        wave_lds_sync();  // the next tile reuses this wave's LDS slice
-    }
-    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
-}
 
 template <int TEX>
 __global__ void k_texel_eval(DevTexture T, const int2* __restrict__ xy, int64_t n,
@@ -366,45 +18,14 @@ __global__ void k_texel_eval(DevTexture T, const int2* __restrict__ xy, int64_t 
     }
 }
 
-template <int METHOD, int TEX>
-hipError_t launch_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
-{
-    // grid-stride over tiles: up to 8 workgroups per CU, several tiles per wave
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
-    const dim3 grid((unsigned)blocks);
-    const dim3 block(kWave * kWavesPerBlock);
-    if (a.tile_stats)
-        hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true>), grid, block, 0, s, a, T);
-    else
-        hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false>), grid, block, 0, s, a, T);
-    return hipGetLastError();
-}
-
-template <int TEX>
-hipError_t launch_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
-{
-    switch (a.method) {
-    case CTF_BILINEAR4: return launch_m_t<CTF_BILINEAR4, TEX>(a, T, s);
-    case CTF_STF1: return launch_m_t<CTF_STF1, TEX>(a, T, s);
-    case CTF_LIST: return launch_m_t<CTF_LIST, TEX>(a, T, s);
-    case CTF_BOX: return launch_m_t<CTF_BOX, TEX>(a, T, s);
-    case CTF_MASK: return launch_m_t<CTF_MASK, TEX>(a, T, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 }  // namespace
 
 hipError_t launch_filter_simt(const FilterArgs& a, const DevTexture& T, hipStream_t s)
 {
-    switch (T.kind) {
-    case CTF_TEX_SINUSOIDS: return launch_t<CTF_TEX_SINUSOIDS>(a, T, s);
-    case CTF_TEX_AFFINE: return launch_t<CTF_TEX_AFFINE>(a, T, s);
-    case CTF_TEX_CONSTANT: return launch_t<CTF_TEX_CONSTANT>(a, T, s);
-    case CTF_TEX_TABLE: return launch_t<CTF_TEX_TABLE>(a, T, s);
+    switch (a.filter) {
+    case CTF_FILTER_BILINEAR: return simt::launch_filter<CTF_FILTER_BILINEAR>(a, T, s);
+    case CTF_FILTER_BSPLINE:
+    case CTF_FILTER_CATMULL_ROM: return launch_filter_simt_cubic(a, T, s);
     default: return hipErrorInvalidValue;
     }
 }

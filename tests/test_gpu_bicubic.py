@@ -1,0 +1,102 @@
+"""GPU parity of the bicubic filters (Section 5: B-spline, Catmull-Rom; 4x4
+footprints) on the per-lane producer, against the oracle.
+
+Decisions, lists, draws and counts exact.  Colours within 2e-6 of the
+float64 oracle: each procedural texel is within 3e-7 of float64, the 16
+weights have sum |w| <= 1.27 (Catmull-Rom's largest), and the float32
+weighting adds at most 16 roundings of the running sum (<= 1.3 ulp of 1 each).
+"""
+import numpy as np
+import pytest
+
+import ctf_synth as cs
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_CUBIC = 2e-6
+FILTERS = [("bspline", O.FILTER_BSPLINE), ("catmull_rom", O.FILTER_CATMULL_ROM)]
+METHODS = [("full", 0, O.BILINEAR4, (0, 0), 1), ("stf1", 1, O.STF1, (0, 0), 1),
+           ("list", 2, O.LIST, (0, 0), 1), ("list_k2", 2, O.LIST, (0, 0), 2),
+           ("box", 3, O.BOX, (0, 0), 1), ("box6x6_k2", 3, O.BOX, (6, 6), 2),
+           ("mask", 4, O.MASK, (0, 0), 1), ("mask_k4", 4, O.MASK, (0, 0), 4)]
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    import paper_2506_17770_amd as ctf
+    ctx = ctf.Context(0)
+    yield ctf, ctx, torch
+    ctx.close()
+
+
+def _scenes():
+    from test_gpu_filter import _edge_scene
+    sc = cs.tilted_plane_scene()
+    return [("plane", (sc.uv, sc.duv)), ("edge", _edge_scene()),
+            ("quads", cs.lowmag_quads_scene(300, seed=31, tex_w=64, mag=(0.9, 4.0)))]
+
+
+@pytest.mark.parametrize("fname,flt", FILTERS)
+@pytest.mark.parametrize("name,gk,ok,box,k", METHODS)
+def test_bicubic_parity(G, fname, flt, name, gk, ok, box, k):
+    from test_gpu_filter import compare, run_gpu
+    ctf, ctx, _ = G
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=5)
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    otex = O.sinusoid_texture(64, pqj, amp)
+    for sname, (uv, duv) in _scenes():
+        g = run_gpu(G, uv, duv, tex, ctf.method(gk, box=box, k=k, filter=flt), seed=13)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box, k=k, filter=flt), seed=13, lists=True, stf=True)
+        compare(g, o, f"{fname} {name} {sname}", tol=TOL_CUBIC)
+        if gk == 2 and k == 2 and sname == "edge":   # the sorted (past 16x16) List path ran
+            st = o["stats"]
+            assert np.any((st["bbw"] > 16) & ((st["flags"] & O.TILE_OK) != 0))
+    tex.close()
+
+
+@pytest.mark.parametrize("fname,flt", FILTERS)
+@pytest.mark.parametrize("gk,k", [(2, 2), (3, 4), (4, 2)])
+def test_bicubic_collaborative_equals_full_bitwise(G, fname, flt, gk, k):
+    from test_gpu_filter import run_gpu
+    ctf, ctx, _ = G
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=6)
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    sc = cs.tilted_plane_scene()
+    full = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(0, filter=flt))
+    col = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(gk, k=k, filter=flt))
+    exact = col["stf"][..., 0] == np.iinfo(np.int32).min
+    assert exact.sum() > 5000
+    assert np.array_equal(full["out"][exact], col["out"][exact])
+    assert col["frame"]["evals"] < full["frame"]["evals"] / 3
+    tex.close()
+
+
+@pytest.mark.parametrize("fname,flt", FILTERS)
+@pytest.mark.parametrize("fb", [O.FB_C, O.FB_CPLUS])
+@pytest.mark.parametrize("gk,ok,box", [(2, O.LIST, (0, 0)), (3, O.BOX, (0, 0)), (4, O.MASK, (0, 0))])
+def test_bicubic_fallback_parity(G, fname, flt, fb, gk, ok, box):
+    from test_gpu_filter import compare, run_gpu
+    ctf, ctx, _ = G
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=7)
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    otex = O.sinusoid_texture(64, pqj, amp)
+    for sname, (uv, duv) in _scenes()[1:]:
+        g = run_gpu(G, uv, duv, tex, ctf.method(gk, box=box, fallback=fb, filter=flt), seed=21)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box, fallback=fb, filter=flt), seed=21, lists=True,
+                     stf=True)
+        compare(g, o, f"{fname} fb{fb} {sname}", tol=TOL_CUBIC)
+    tex.close()
+
+
+def test_bicubic_rejected_on_decoder_producer(G):
+    ctf, ctx, torch = G
+    dec = ctx.decoder(16, 4, 64, 64, cs.decoder_init(16, 4, 64, seed=1))
+    tex = ctx.decoder_texture(dec, 0)
+    sc = cs.tilted_plane_scene()
+    with pytest.raises(ctf.CtfError, match="bilinear"):
+        ctx.filter(torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda(), tex,
+                   ctf.method(ctf.LIST, filter=ctf.FILTER_BSPLINE))
+    tex.close()
+    dec.close()

@@ -55,8 +55,8 @@ def run_gpu(G, uv, duv, tex, meth, seed=0):
                 lists=li.cpu().numpy(), stf=sx.cpu().numpy())
 
 
-def compare(g, o, what=""):
-    """Full parity of one frame: decisions exact, colours within TOL."""
+def compare(g, o, what="", tol=TOL):
+    """Full parity of one frame: decisions exact, colours within tol."""
     for f in STAT_FIELDS:
         a, b = g["stats"][f], o["stats"][f]
         bad = np.flatnonzero((a != b).reshape(len(a), -1).any(-1))
@@ -67,7 +67,7 @@ def compare(g, o, what=""):
         assert np.array_equal(g["lists"][t, :n], o["lists"][t, :n]), f"{what}: list of tile {t}"
     assert np.array_equal(g["stf"], o["stf"]), f"{what}: STF draws differ"
     err = np.abs(g["out"].astype(np.float64) - o["out"])
-    assert err.max() <= TOL, f"{what}: max colour error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+    assert err.max() <= tol, f"{what}: max colour error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
     st = o["stats"]
     fr = g["frame"]
     assert fr["evals"] == int(st["evals"].sum())
