@@ -51,6 +51,7 @@ def parse():
                     help="run one 256 MiB device copy first (scale for the HBM byte counters)")
     ap.add_argument("--no-procedural", action="store_true", help="skip the 1080p procedural-texture runs")
     ap.add_argument("--no-layers", action="store_true", help="skip the six-layer 4K runs")
+    ap.add_argument("--no-bicubic", action="store_true", help="skip the bicubic 4K runs")
     ap.add_argument("--layers", type=int, default=6)
     return ap.parse_args()
 
@@ -346,6 +347,25 @@ def main():
         "wall_s": {"collaborative": wall_col, "bilinear4": wall_b4},
         "roofline": roof,
     }
+    if not args.no_bicubic:
+        log("bench: bicubic filters at 4K")
+        bic = {}
+        for fname, flt in (("bspline", ctf.FILTER_BSPLINE), ("catmull_rom", ctf.FILTER_CATMULL_ROM)):
+            for mname, m in (("list_k4", ctf.method(ctf.LIST, k=4, filter=flt)),
+                             ("full16", ctf.method(ctf.BILINEAR4, filter=flt))):
+                st = stats(m)
+                _, per = timed(lambda: ctx.filter(uv, duv, dtex, m, seed=seed_stf, out=out), stream,
+                               max(3, args.steps // 2), 2, torch)
+                ms = float(np.mean(per))
+                tfl = st["evals"] * MLP_FLOP / (ms * 1e-3) / 1e12
+                bic[f"{fname}_{mname}"] = {"gpixels_per_s": npx / (ms * 1e-3) / 1e9, "ms": ms,
+                                           "texel_evals_per_pixel": st["evals"] / npx,
+                                           "not_exact_fraction": st["stf"] / max(1, st["active"]),
+                                           "mfma_tflops": tfl, "mfma_frac": tfl / PEAK_FP16_TFLOPS}
+            bic[f"{fname}_speedup_vs_full16"] = (bic[f"{fname}_list_k4"]["gpixels_per_s"] /
+                                                 bic[f"{fname}_full16"]["gpixels_per_s"])
+        res["bicubic_4k"] = {"workload": "the 4K frame and fp16 decoder above with 4x4 bicubic footprints: List "
+                                         "k=4 + one-tap draw by |w| vs all 16 taps decoded per pixel", "runs": bic}
     if not args.no_procedural:
         log("bench: 1080p procedural texture")
         res["procedural_1080p"] = bench_procedural(ctx, ctf, cs, torch, args, stream)

@@ -163,7 +163,7 @@ typedef struct ctf_method {
     int32_t mask_side;           /* CTF_MASK: 16 */
     int32_t max_evals_per_lane;  /* k in 1..4: a wave succeeds when n <= k * |A| */
     int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
-    int32_t filter;              /* CTF_FILTER_*; the decoder producer takes bilinear only */
+    int32_t filter;              /* CTF_FILTER_*; ctf_filter_layers takes bilinear only */
 } ctf_method;
 
 /* One record per tile (128 bytes). */
@@ -231,7 +231,7 @@ ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
  * [n_layers][tiles]; debug_stf: nullable device int32 [n_layers][sh][sw][2];
  * frame_stats: nullable, totals over all layers.  Other arguments as for
  * ctf_filter.  Errors: CTF_ERR_INVALID_ARG, CTF_ERR_UNSUPPORTED (non-decoder
- * texture, mixed precisions). */
+ * texture, mixed precisions, a filter other than CTF_FILTER_BILINEAR). */
 ctf_status ctf_filter_layers(ctf_context ctx, const float *uv, const float *uv_derivs,
                              int32_t sw, int32_t sh, int32_t n_layers, const ctf_texture *texs,
                              const float *xforms, const ctf_method *method, uint64_t seed,

@@ -281,7 +281,7 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_d
     ctf_status st = check_method(m, "ctf_filter_layers");
     if (st != CTF_OK) return st;
     if (m->filter != CTF_FILTER_BILINEAR)
-        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the decoder producer takes the bilinear filter only");
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the layered launch takes the bilinear filter only");
     for (int l = 0; l < n_layers; ++l) {
         if (!texs[l] || texs[l]->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: texture %d", l);
         if (texs[l]->dev.kind != CTF_TEX_DECODER || texs[l]->dec.precision != texs[0]->dec.precision)
@@ -310,8 +310,6 @@ ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, 
     ctf_status st = check_method(m, "ctf_filter");
     if (st != CTF_OK) return st;
     if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");
-    if (tex->dev.kind == CTF_TEX_DECODER && m->filter != CTF_FILTER_BILINEAR)
-        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: the decoder producer takes the bilinear filter only");
     DeviceScope ds(ctx->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_filter: set device");
 

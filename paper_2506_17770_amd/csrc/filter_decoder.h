@@ -1,0 +1,594 @@
+// filter_decoder.h -- collaborative filtering with the learned texel producer.
+//
+// Same decisions as the per-lane path (Sections 3.1-3.3, remapping, the
+// fallbacks of Section 3.4 and the bicubic filters of Section 5), but texel
+// production is batched: the wave writes the (x, y) of every texel it must
+// produce into an LDS row list (the unique texels first, then one row per
+// one-tap draw; in a wave that takes fallback C or C+, the planned texels of
+// A, then the minifying lanes' draws) and decodes the rows 16 at a time on
+// MFMA (decoder_mlp.h).  Dedup therefore turns the per-tap decode into one
+// dense MLP pass over the wave's distinct texels.
+//
+// Waves are persistent: each loads the MLP weights into registers once and
+// walks a band of tiles.  Workgroups are dispatched round-robin over the 8
+// XCDs; band b of the screen goes to the workgroups of XCD b so that the
+// latent-grid reads of neighbouring tiles share an L2.
+//
+// Instantiated per reconstruction filter (FxF footprints, F = 2 or 4): the
+// bilinear kernels in filter_decoder.hip, the bicubic ones in
+// filter_decoder_cubic.hip.
+#pragma once
+
+#include <stddef.h>
+
+#include "ctf_device.h"
+#include "ctf_internal.h"
+#include "decoder_mlp.h"
+#include "fallback.h"
+
+namespace ctf {
+
+namespace dec {
+
+constexpr int kDecWaves = 4;
+
+// vals, rows and keys are contiguous: the bicubic List sort uses the three
+// as one 1024-key buffer before any row or value exists.
+struct DecLds {
+    float4 vals[kMaxItems];     // decoded texels, by row
+    int2 rows[kMaxItems];       // texel coordinates to decode
+    uint64_t keys[kMaxItems];   // List past 16x16 (bilinear): sorted unique keys
+    uint8_t rank[256];          // Mask/List: position t -> row (h^-1)
+    uint8_t bytes[256];         // footprint-corner scatter before the ballots
+};
+static_assert(offsetof(DecLds, rows) == 16 * kMaxItems && offsetof(DecLds, keys) == 24 * kMaxItems,
+              "sort buffer layout");
+
+// Sort buffer of the List past 16x16: F^2 keys per lane.
+template <int F>
+__device__ __forceinline__ uint64_t* dec_keys(DecLds& L)
+{
+    if constexpr (F == 2) return L.keys;
+    else return reinterpret_cast<uint64_t*>(&L);
+}
+
+// Exact set of the wave's texels as sorted unique keys (any box size): a
+// bitonic sort of the F^2 |A| footprint keys, then compaction of the first
+// key of every run.  Returns n = |U|; dec_keys<F>(L)[0..n) hold U in (y, x)
+// order.
+template <int F>
+__device__ int dec_list_sorted(DecLds& L, bool inA, int ox, int oy, int xmin, int ymin)
+{
+    constexpr int N = kWave * F * F;
+    uint64_t* keys = dec_keys<F>(L);
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < F * F; ++q) {
+        uint64_t key = ~0ull;
+        if (inA)
+            key = ((uint64_t)(uint32_t)(oy + q / F - ymin) << 32) | (uint32_t)(ox + q % F - xmin);
+        keys[F * F * lane + q] = key;
+    }
+    for (int size = 2; size <= N; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            wave_lds_sync();
+#pragma unroll
+            for (int h = 0; h < N / (2 * kWave); ++h) {
+                const int p = lane + kWave * h;
+                const int i = (p / stride) * stride * 2 + (p % stride);
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint64_t x = keys[i], y = keys[j];
+                if ((x > y) == up) {
+                    keys[i] = y;
+                    keys[j] = x;
+                }
+            }
+        }
+    // compaction in rounds of 64 keys: a write index never passes the read
+    // index, and round r writes below every key of the later rounds
+    int base = 0;
+    for (int c = 0; c < F * F; ++c) {
+        wave_lds_sync();
+        const int i = kWave * c + lane;
+        const uint64_t k = keys[i];
+        const bool first = k != ~0ull && (i == 0 || keys[i - 1] != k);
+        const uint64_t b = ballot(first);
+        wave_lds_sync();
+        if (first) keys[base + mbcnt(b)] = k;
+        base += popc64(b);
+    }
+    wave_lds_sync();
+    return base;
+}
+
+__device__ __forceinline__ int dec_list_find(const uint64_t* keys, int n, uint64_t key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int P>
+__device__ __forceinline__ void fetch_row(const int2* rows, int R, int row, const LatentGrid& G, int g,
+                                          LatentFetch& F)
+{
+    const int2 p = row < R ? rows[row] : make_int2(0, 0);
+    latent_fetch(G, p.x, p.y, g, F);
+}
+
+template <int P>
+__device__ __forceinline__ void finish_row(float4* vals, int R, int row, const FwdWeights<P>& W,
+                                           const Biases& Bz, const LatentFetch& F, int g)
+{
+    const f4 y = mlp_forward<P>(W, Bz, latent_combine<P>(F), nullptr, nullptr);
+    if (g == 0 && row < R) vals[row] = make_float4(y[0], y[1], y[2], y[3]);
+}
+
+// rows[0..R) -> vals[0..R) in 16-row tiles, two fetch buffers in ping-pong.
+// Every prefetch is issued unconditionally (rows past R fetch cell 0), so
+// each path reaches the next tile's MLP with the same loads outstanding and
+// the wait before it covers only the current tile's gathers.
+template <int P>
+__device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& G, const FwdWeights<P>& W,
+                                            const Biases& Bz, int j, int g)
+{
+    const int T = (R + 15) >> 4;
+    if (T == 0) return;
+    LatentFetch fa, fb;
+    fetch_row<P>(L.rows, R, j, G, g, fa);
+    for (int t = 0; t < T; t += 2) {
+        fetch_row<P>(L.rows, R, 16 * (t + 1) + j, G, g, fb);
+        finish_row<P>(L.vals, R, 16 * t + j, W, Bz, fa, g);
+        if (t + 1 >= T) break;
+        fetch_row<P>(L.rows, R, 16 * (t + 2) + j, G, g, fa);
+        finish_row<P>(L.vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
+    }
+}
+
+__device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t tile, uint64_t act, uint64_t A,
+                                                 uint64_t stfmask, bool fits16, const uint64_t B[4], int xmin,
+                                                 int ymin, int bbw, int bbh, int n, int unique, int evals,
+                                                 bool success, bool cap_ok, bool count_ok, int nA)
+{
+    ctf_tile_stats S;
+    S.active = act;
+    S.part = A;
+    S.stf = stfmask;
+    for (int w = 0; w < 4; ++w) S.mask[w] = fits16 ? B[w] : 0ull;
+    S.xmin = xmin;
+    S.ymin = ymin;
+    S.bbw = bbw;
+    S.bbh = bbh;
+    S.n = n;
+    S.unique = unique;
+    S.evals = evals;
+    S.flags = (success ? CTF_TILE_OK : 0) | (nA && !cap_ok ? CTF_TILE_CAP : 0) |
+              (nA && cap_ok && !count_ok ? CTF_TILE_OVERFLOW : 0) | (nA == 0 ? CTF_TILE_EMPTY : 0);
+    for (int r = 0; r < 10; ++r) S.reserved[r] = 0;
+    a.tile_stats[tile] = S;
+}
+
+// One tile of the decoder-path filter: decisions, row list, MFMA decode,
+// gather and outputs.  `f` is the lanes' footprint (already in this
+// layer's coordinates); a.out / a.tile_stats / a.stf_xy point at this
+// layer's planes.
+template <int METHOD, int P, bool STATS, bool FB, int FILTER>
+__device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& G, const FwdWeights<P>& W,
+                                         const Biases& Bz, DecLds& L, int64_t tile, int tx, int ty,
+                                         const Footprint& f, FrameCounters& fc)
+{
+    constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
+    const int lane = lane_id();
+    const int j = lane & 15, g = lane >> 4;
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    const bool in_screen = px < a.sw && py < a.sh;
+    const int64_t pix = (int64_t)py * a.sw + px;
+    const int ox = f.x0 - O, oy = f.y0 - O;   // upper-left tap of the FxF footprint
+    const bool inA = f.active && f.magnify;
+    const uint64_t act = ballot(f.active);
+    const uint64_t A = ballot(inA);
+    const int nA = popc64(A);
+
+    int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
+    constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    if ((kCollab || STATS) && nA > 0) {
+        xmin = wave_min(inA ? ox : INT32_MAX);
+        ymin = wave_min(inA ? oy : INT32_MAX);
+        bbw = wave_max(inA ? ox + F - 1 : INT32_MIN) - xmin + 1;
+        bbh = wave_max(inA ? oy + F - 1 : INT32_MIN) - ymin + 1;
+    }
+    const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+
+    // ---- 16x16 wave mask B (Mask Sampling; also the exact set when it
+    // fits).  Each lane of A marks only its footprint's upper-left texel
+    // (mask C, one LDS byte and four ballots); B is C spread over the FxF
+    // footprint with 256-bit shifts (rows of 16 do not wrap when the box
+    // fits).
+    uint64_t B[4] = {0, 0, 0, 0};
+    int nmask = 0;
+    constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
+    if (kNeedMask && fits16) {
+        reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
+        wave_lds_sync();
+        if (inA) L.bytes[16 * (oy - ymin) + (ox - xmin)] = 1;
+        wave_lds_sync();
+        uint64_t C[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) C[w] = ballot(L.bytes[64 * w + lane] != 0);
+        footprint_mask_f<F>(C, B);
+        nmask = popc64(B[0]) + popc64(B[1]) + popc64(B[2]) + popc64(B[3]);
+    }
+
+    const int k = a.max_evals;
+    int n = 0;
+    bool cap_ok = true, count_ok = true, success = false, sorted = false;
+    int unique = nmask;
+    if constexpr (METHOD == CTF_BOX) {
+        const int64_t area = (int64_t)bbw * bbh;
+        n = area > INT32_MAX ? INT32_MAX : (int)area;
+        cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
+        count_ok = area <= (int64_t)k * nA;
+        success = nA > 0 && cap_ok && count_ok;
+    } else if constexpr (METHOD == CTF_MASK) {
+        cap_ok = fits16;
+        n = fits16 ? nmask : 0;
+        count_ok = n <= k * nA;
+        success = fits16 && count_ok;
+    } else if constexpr (METHOD == CTF_LIST) {
+        if (nA > 0 && !fits16) {
+            n = dec_list_sorted<F>(L, inA, ox, oy, xmin, ymin);
+            sorted = true;
+        } else {
+            n = nmask;
+        }
+        unique = n;
+        count_ok = n <= k * nA;
+        success = nA > 0 && count_ok;
+    }
+    if constexpr (STATS && METHOD != CTF_LIST) {
+        if (nA > 0 && !fits16) unique = dec_list_sorted<F>(L, inA, ox, oy, xmin, ymin);
+    }
+    if (nA == 0) unique = 0;
+
+    bool exact, draws;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        exact = f.active;
+        draws = false;
+    } else if constexpr (METHOD == CTF_STF1) {
+        exact = false;
+        draws = f.active;
+    } else {
+        exact = inA && success;
+        draws = f.active && !exact;
+    }
+    const uint64_t stfmask = ballot(draws);
+    const int nstf = popc64(stfmask);
+    int2 pick = make_int2(INT32_MIN, INT32_MIN);
+    uint32_t h1 = 0, h2 = 0;
+    if (draws) {
+        stf_hashes(a.seed, a.layer, px, py, h1, h2);
+        pick = stf_pick_filter<FILTER>(f, h1, h2);
+    }
+    const int rank_act = mbcnt(act);
+
+    if constexpr (METHOD == CTF_BILINEAR4 && F == 4) {
+        // ---- the full 4x4 filter: 16 taps per active lane do not fit one
+        // row list, so the footprint rows are decoded one at a time (4 taps
+        // per lane, up to 256 rows) and accumulated as in the gather below
+        float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int R = 4 * popc64(act);
+        for (int jr = 0; jr < 4; ++jr) {
+            if (f.active) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) L.rows[4 * rank_act + i] = make_int2(ox + i, oy + jr);
+            }
+            wave_lds_sync();
+            decode_rows<P>(L, R, G, W, Bz, j, g);
+            wave_lds_sync();
+            if (exact) {
+                float wx[4], wy[4];
+                taps32<FILTER>(f.s, wx);
+                taps32<FILTER>(f.t, wy);
+                const int b = 4 * rank_act;
+                const float4 r = row4(wx, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
+                res = col_acc(wy[jr], r, res, jr == 0);
+            }
+            wave_lds_sync();
+        }
+        if (in_screen) {
+            reinterpret_cast<float4*>(a.out)[pix] = res;
+            if (a.stf_xy) reinterpret_cast<int2*>(a.stf_xy)[pix] = make_int2(INT32_MIN, INT32_MIN);
+        }
+        if (lane == 0 && a.tile_stats)
+            write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, 4 * R, success,
+                             cap_ok, count_ok, nA);
+        if (act) fc.add(4 * R, popc64(act), nstf, popc64(act & ~A), 4 * ((R + 15) & ~15), false, false);
+        return;
+    }
+
+    // fallback C / C+ for the lanes of A of a failed wave (fallback.h)
+    const bool fallback = FB && !success && nA > 0;
+    const uint64_t mdraw = stfmask & ~A;   // minifying draws in a fallback wave
+    FallbackPlan fp{};
+
+    // ---- row list: the texels to produce (unique texels first, in the
+    // method's order, then one row per fallback draw) and the inverse table
+    // of Mask/List
+    const int ns = success ? n : 0;
+    // List past 16x16: per-lane item indices of the F^2 taps, found before
+    // the decode (bilinear: the rank table; bicubic: the keys array, free
+    // once the sorted keys sit at the front of the sort buffer)
+    uint8_t* const sidx = F == 2 ? L.rank : reinterpret_cast<uint8_t*>(L.keys);
+    int R;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        R = 4 * popc64(act);
+        if (f.active) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L.rows[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
+        }
+    } else if (fallback) {
+        fp = plan_fallback<FILTER>(L, a.fallback, inA, nA, mbcnt(A), f, pick, pcg_hash(h2), fits16, xmin, ymin);
+        R = fp.nprod + popc64(mdraw);
+        if (fp.produces) L.rows[fp.slot] = fp.texel;
+        if (draws && !inA) L.rows[fp.nprod + mbcnt(mdraw)] = pick;
+    } else {
+        R = ns + nstf;
+        if (success) {
+            if (METHOD == CTF_BOX || sorted) {
+                const uint64_t* keys = dec_keys<F>(L);
+                for (int i = lane; i < ns; i += kWave) {
+                    int ex, ey;
+                    if (METHOD == CTF_BOX) {
+                        ex = xmin + i % bbw;
+                        ey = ymin + i / bbw;
+                    } else {
+                        const uint64_t key = keys[i];
+                        ex = xmin + (int)(uint32_t)key;
+                        ey = ymin + (int)(key >> 32);
+                    }
+                    L.rows[i] = make_int2(ex, ey);
+                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+                }
+            } else {
+                // set bit t of B with rank r: row r, and rank[t] = r (h^-1)
+                int base = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if ((B[w] >> lane) & 1u) {
+                        const int r = base + mbcnt(B[w]);
+                        const int t = 64 * w + lane;
+                        const int2 c = make_int2(xmin + (t & 15), ymin + (t >> 4));
+                        L.rank[t] = (uint8_t)r;
+                        L.rows[r] = c;
+                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
+                    }
+                    base += popc64(B[w]);
+                }
+            }
+            if (sorted && inA) {
+                const uint64_t* keys = dec_keys<F>(L);
+#pragma unroll
+                for (int q = 0; q < F * F; ++q) {
+                    const uint64_t key = ((uint64_t)(uint32_t)(oy + q / F - ymin) << 32) |
+                                         (uint32_t)(ox + q % F - xmin);
+                    sidx[F * F * lane + q] = (uint8_t)dec_list_find(keys, n, key);
+                }
+            }
+        }
+        if (draws) L.rows[ns + mbcnt(stfmask)] = pick;
+    }
+    // the debug draws are known now; write them before the decode so the
+    // draw is not kept live across it
+    if (in_screen && a.stf_xy)
+        reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+    // where this lane's taps sit: tap (i, j) has item index gi + i + gd j
+    // (Box: directly; Mask and List: through the table at gi)
+    int gi = 0, gd = 0;
+    if constexpr (METHOD == CTF_BOX) {
+        gi = (ox - xmin) + (oy - ymin) * bbw;
+        gd = bbw;
+    } else if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
+        gi = sorted ? F * F * lane : 16 * (oy - ymin) + (ox - xmin);
+        gd = sorted ? F : 16;
+    }
+    const int draw_row = ns + mbcnt(stfmask);
+    wave_lds_sync();
+
+    // ---- decode the rows, 16 per MFMA tile; the latent gathers of the
+    // next tile are in flight during the MLP of the current one
+    decode_rows<P>(L, R, G, W, Bz, j, g);
+    wave_lds_sync();
+
+    // ---- gather and weight
+    float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        if (exact) {
+            const int b = 4 * rank_act;
+            res = bilerp(f.s, f.t, L.vals[b], L.vals[b + 1], L.vals[b + 2], L.vals[b + 3]);
+        }
+    } else if (fallback) {
+        if (draws && !inA) res = L.vals[fp.nprod + mbcnt(mdraw)];
+        if (inA) res = fallback_color<FILTER>(L, fp, f, pick, xmin, ymin);
+    } else {
+        if (draws) res = L.vals[draw_row];
+        if (kCollab && exact) {
+            const uint8_t* tab = sorted ? sidx : L.rank;
+            auto item = [&](int i, int jj) -> int {
+                const int t = gi + i + gd * jj;
+                if constexpr (METHOD == CTF_BOX) return t;
+                else return tab[t];
+            };
+            if constexpr (F == 2) {
+                res = bilerp(f.s, f.t, L.vals[item(0, 0)], L.vals[item(1, 0)], L.vals[item(0, 1)],
+                             L.vals[item(1, 1)]);
+            } else {
+                float wx[4], wy[4];
+                taps32<FILTER>(f.s, wx);
+                taps32<FILTER>(f.t, wy);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float4 r = row4(wx, L.vals[item(0, jj)], L.vals[item(1, jj)], L.vals[item(2, jj)],
+                                          L.vals[item(3, jj)]);
+                    res = col_acc(wy[jj], r, res, jj == 0);
+                }
+            }
+        }
+    }
+    if (in_screen) reinterpret_cast<float4*>(a.out)[pix] = res;
+    if (lane == 0 && a.tile_stats)
+        write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, R, success, cap_ok,
+                         count_ok, nA);
+    if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), (R + 15) & ~15, kCollab && success,
+                    kCollab && nA && !success);
+    wave_lds_sync();  // the next tile reuses this wave's LDS slice
+}
+
+// Inputs of a tile for this lane, NaN (inactive) outside the band or screen.
+__device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
+                                             float4& d)
+{
+    const int lane = lane_id();
+    uv = make_float2(__builtin_nanf(""), 0.f);
+    d = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t.tile >= band_e) return;
+    const int px = t.tx * kTile + (lane & 7), py = t.ty * kTile + (lane >> 3);
+    if (px < a.sw && py < a.sh) {
+        const int64_t q = (int64_t)py * a.sw + px;
+        uv = reinterpret_cast<const float2*>(a.uv)[q];
+        d = reinterpret_cast<const float4*>(a.duv)[q];
+    }
+}
+
+// XCD-aware band of tiles for this wave: workgroups go round-robin over the
+// 8 XCDs, so band b of the screen is walked by the workgroups of XCD b.
+struct Band {
+    int64_t begin, end;
+    int lw, nw;
+    __device__ Band(int64_t ntiles, int wid)
+    {
+        const int xcd = blockIdx.x & 7;
+        lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
+        nw = (int)(gridDim.x >> 3) * kDecWaves;
+        begin = ntiles * xcd / 8;
+        end = ntiles * (xcd + 1) / 8;
+    }
+};
+
+// Waves per SIMD the register budget of the single-layer kernel is sized
+// for: the collaborative methods and the 4x4 full filter need the bound of
+// three to fit in 168 registers; the others fit three anyway and keep the
+// compiler's schedule.
+template <int METHOD, int FILTER>
+constexpr int dec_waves_per_simd()
+{
+    return METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK ||
+                   (METHOD == CTF_BILINEAR4 && FILTER != CTF_FILTER_BILINEAR)
+               ? 3
+               : 2;
+}
+
+template <int METHOD, int P, bool STATS, bool FB, int FILTER>
+__global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>())) void k_filter_dec(
+    FilterArgs a, DevDecoderWeights D)
+{
+    __shared__ DecLds lds_all[kDecWaves];
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    DecLds& L = lds_all[wid];
+    FwdWeights<P> W;
+    W.load(D.w, lane);
+    Biases Bz;
+    Bz.load(D.bias, lane);
+    const float tex_w = (float)D.grid.tex_w;
+    const Band band(a.ntiles, wid);
+    FrameCounters fc;
+
+    // the inputs of the wave's next tile are loaded one tile ahead
+    float2 uv_next;
+    float4 d_next;
+    TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+    load_tile_px(a, next, band.end, uv_next, d_next);
+    while (next.tile < band.end) {
+        const TileWalk cur = next;
+        const float2 uv = uv_next;
+        const float4 d = d_next;
+        next.advance(band.nw);
+        load_tile_px(a, next, band.end, uv_next, d_next);
+        const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
+        dec_tile<METHOD, P, STATS, FB, FILTER>(a, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
+    }
+    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
+}
+
+inline int device_cus()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+
+// Persistent grid: as many workgroups as fit on the device at once (from the
+// kernel's register and LDS use), a multiple of the 8 XCDs.
+template <typename K>
+int64_t resident_blocks(K kernel, int threads, int64_t work_blocks)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int64_t blocks = (int64_t)device_cus() * per_cu;
+    if (blocks > work_blocks) blocks = work_blocks;
+    return (blocks + 7) / 8 * 8;
+}
+
+constexpr bool collaborative(int m) { return m == CTF_LIST || m == CTF_BOX || m == CTF_MASK; }
+
+// Instantiation for the call's statistics and fallback flags; waves of a
+// collaborative method carry the C / C+ code only when it is asked for, so
+// the common path keeps its register budget.
+template <int METHOD, int P, template <int, int, bool, bool> class Go, class... Args>
+hipError_t dispatch_flags(const FilterArgs& a, Args&&... args)
+{
+    const bool st = a.tile_stats != nullptr;
+    if constexpr (collaborative(METHOD)) {
+        if (a.fallback != CTF_FB_STF1)
+            return st ? Go<METHOD, P, true, true>::run(a, args...) : Go<METHOD, P, false, true>::run(a, args...);
+    }
+    return st ? Go<METHOD, P, true, false>::run(a, args...) : Go<METHOD, P, false, false>::run(a, args...);
+}
+
+template <int FILTER>
+struct GoFilter {
+    template <int METHOD, int P, bool STATS, bool FB>
+    struct Go {
+        static hipError_t run(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
+        {
+            const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+            auto k = k_filter_dec<METHOD, P, STATS, FB, FILTER>;
+            const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+            return hipGetLastError();
+        }
+    };
+};
+
+template <int P, int FILTER>
+hipError_t launch_dec_p(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
+{
+    switch (a.method) {
+    case CTF_BILINEAR4: return dispatch_flags<CTF_BILINEAR4, P, GoFilter<FILTER>::template Go>(a, d, s);
+    case CTF_STF1: return dispatch_flags<CTF_STF1, P, GoFilter<FILTER>::template Go>(a, d, s);
+    case CTF_LIST: return dispatch_flags<CTF_LIST, P, GoFilter<FILTER>::template Go>(a, d, s);
+    case CTF_BOX: return dispatch_flags<CTF_BOX, P, GoFilter<FILTER>::template Go>(a, d, s);
+    case CTF_MASK: return dispatch_flags<CTF_MASK, P, GoFilter<FILTER>::template Go>(a, d, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dec
+
+}  // namespace ctf

@@ -1,0 +1,18 @@
+// filter_decoder_cubic.hip -- decoder-path filter kernels for the bicubic
+// filters of Section 5 (uniform cubic B-spline, Catmull-Rom; 4x4 footprints).
+#include "filter_decoder.h"
+
+using namespace ctf;
+using namespace ctf::dec;
+
+hipError_t ctf_internal_decoder_filter_cubic(const ctf_texture_s* t, const FilterArgs& a, hipStream_t s)
+{
+    const DevDecoderWeights& d = t->dec;
+    const bool bf = t->dec.precision == CTF_BF16;
+    if (a.filter == CTF_FILTER_BSPLINE)
+        return bf ? launch_dec_p<CTF_BF16, CTF_FILTER_BSPLINE>(a, d, s) : launch_dec_p<CTF_FP16, CTF_FILTER_BSPLINE>(a, d, s);
+    if (a.filter == CTF_FILTER_CATMULL_ROM)
+        return bf ? launch_dec_p<CTF_BF16, CTF_FILTER_CATMULL_ROM>(a, d, s)
+                  : launch_dec_p<CTF_FP16, CTF_FILTER_CATMULL_ROM>(a, d, s);
+    return hipErrorInvalidValue;
+}

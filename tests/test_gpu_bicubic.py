@@ -1,5 +1,5 @@
 """GPU parity of the bicubic filters (Section 5: B-spline, Catmull-Rom; 4x4
-footprints) on the per-lane producer, against the oracle.
+footprints) on the per-lane and the decoder producers, against the oracle.
 
 Decisions, lists, draws and counts exact.  Colours within 2e-6 of the
 float64 oracle: each procedural texel is within 3e-7 of float64, the 16
@@ -90,13 +90,73 @@ def test_bicubic_fallback_parity(G, fname, flt, fb, gk, ok, box):
     tex.close()
 
 
-def test_bicubic_rejected_on_decoder_producer(G):
+DEC_METHODS = [("full", 0, O.BILINEAR4, (0, 0), 1), ("stf1", 1, O.STF1, (0, 0), 1),
+               ("list_k4", 2, O.LIST, (0, 0), 4), ("list", 2, O.LIST, (0, 0), 1),
+               ("box_k4", 3, O.BOX, (0, 0), 4), ("mask_k2", 4, O.MASK, (0, 0), 2)]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("fname,flt", FILTERS)
+@pytest.mark.parametrize("name,gk,ok,box,k", DEC_METHODS)
+def test_bicubic_decoder_parity(G, prec, fname, flt, name, gk, ok, box, k):
+    """Decoder producer: the oracle filters the GPU-decoded texel lattice."""
+    from test_gpu_decoder import _decoder_case, _lattice_table
+    from test_gpu_filter import compare, run_gpu
+    ctf, ctx, torch = G
+    dec, _ = _decoder_case(ctx)
+    tex = ctx.decoder_texture(dec, prec)
+    otex = O.table_texture(_lattice_table(tex, 64, torch))
+    for sname, (uv, duv) in _scenes():
+        g = run_gpu(G, uv, duv, tex, ctf.method(gk, box=box, k=k, filter=flt), seed=29)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box, k=k, filter=flt), seed=29, lists=True, stf=True)
+        compare(g, o, f"decoder {fname} {name} {sname}", tol=TOL_CUBIC)
+    tex.close()
+    dec.close()
+
+
+@pytest.mark.parametrize("fname,flt", FILTERS)
+@pytest.mark.parametrize("fb", [O.FB_C, O.FB_CPLUS])
+def test_bicubic_decoder_fallback_parity(G, fname, flt, fb):
+    from test_gpu_decoder import _decoder_case, _lattice_table
+    from test_gpu_filter import compare, run_gpu
+    ctf, ctx, torch = G
+    dec, _ = _decoder_case(ctx)
+    tex = ctx.decoder_texture(dec, 0)
+    otex = O.table_texture(_lattice_table(tex, 64, torch))
+    for sname, (uv, duv) in _scenes()[1:]:
+        for gk, ok in ((2, O.LIST), (4, O.MASK)):
+            g = run_gpu(G, uv, duv, tex, ctf.method(gk, fallback=fb, filter=flt), seed=31)
+            o = O.filter(uv, duv, otex, O.method(ok, fallback=fb, filter=flt), seed=31, lists=True, stf=True)
+            compare(g, o, f"decoder {fname} fb{fb} {gk} {sname}", tol=TOL_CUBIC)
+    tex.close()
+    dec.close()
+
+
+@pytest.mark.parametrize("fname,flt", FILTERS)
+def test_bicubic_decoder_collaborative_equals_full_bitwise(G, fname, flt):
+    from test_gpu_decoder import _decoder_case
+    from test_gpu_filter import run_gpu
+    ctf, ctx, torch = G
+    dec, _ = _decoder_case(ctx)
+    tex = ctx.decoder_texture(dec, 0)
+    sc = cs.tilted_plane_scene()
+    full = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(0, filter=flt))
+    col = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(2, k=4, filter=flt))
+    exact = col["stf"][..., 0] == np.iinfo(np.int32).min
+    assert exact.sum() > 5000
+    assert np.array_equal(full["out"][exact], col["out"][exact])
+    assert col["frame"]["evals"] < full["frame"]["evals"] / 6
+    tex.close()
+    dec.close()
+
+
+def test_bicubic_rejected_on_layered_launch(G):
     ctf, ctx, torch = G
     dec = ctx.decoder(16, 4, 64, 64, cs.decoder_init(16, 4, 64, seed=1))
     tex = ctx.decoder_texture(dec, 0)
     sc = cs.tilted_plane_scene()
     with pytest.raises(ctf.CtfError, match="bilinear"):
-        ctx.filter(torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda(), tex,
-                   ctf.method(ctf.LIST, filter=ctf.FILTER_BSPLINE))
+        ctx.filter_layers(torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda(), [tex],
+                          np.eye(2, dtype=np.float32)[None], ctf.method(ctf.LIST, filter=ctf.FILTER_BSPLINE))
     tex.close()
     dec.close()
