@@ -148,7 +148,9 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                     ("box6x6", ctf.method(ctf.BOX, box=(6, 6))), ("mask", ctf.method(ctf.MASK)),
                     ("mask_fbC", ctf.method(ctf.MASK, fallback=ctf.FB_C)),
                     ("mask_fbCplus", ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS)),
-                    ("list_k2", ctf.method(ctf.LIST, k=2))):
+                    ("list_k2", ctf.method(ctf.LIST, k=2)),
+                    ("list_no_split", ctf.method(ctf.LIST, split=ctf.SPLIT_OFF)),
+                    ("mask_no_split", ctf.method(ctf.MASK, split=ctf.SPLIT_OFF))):
         fs = ctf.frame_stats_buffer()
         ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs)
         torch.cuda.synchronize()

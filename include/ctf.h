@@ -85,6 +85,14 @@ enum { CTF_FB_STF1 = 0, CTF_FB_C = 1, CTF_FB_CPLUS = 2 };
  * for C+'s draws. */
 enum { CTF_FILTER_BILINEAR = 0, CTF_FILTER_BSPLINE = 1, CTF_FILTER_CATMULL_ROM = 2 };
 
+/* Split-texel production (the idea of Section 5's DCT discussion: spread one
+ * texel's work over idle lanes).  With CTF_SPLIT_AUTO, a procedural-texture
+ * wave whose collaborative step succeeded with no one-tap draws and n <= 32
+ * (n <= 16) texels evaluates each texel on 2 (4) lanes, one channel pair
+ * (one channel) per lane, reading the terms from LDS (textures of at most
+ * 64 terms per channel).  Results are bit-identical either way. */
+enum { CTF_SPLIT_AUTO = 0, CTF_SPLIT_OFF = 1 };
+
 /* Texel producers (Section 3: "produce a texel"). */
 enum {
     CTF_TEX_SINUSOIDS = 0,  /* procedural sum of sinusoids (below) */
@@ -164,6 +172,7 @@ typedef struct ctf_method {
     int32_t max_evals_per_lane;  /* k in 1..4: a wave succeeds when n <= k * |A| */
     int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
     int32_t filter;              /* CTF_FILTER_*; ctf_filter_layers takes bilinear only */
+    int32_t split;               /* CTF_SPLIT_AUTO / CTF_SPLIT_OFF (procedural textures) */
 } ctf_method;
 
 /* One record per tile (128 bytes). */

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libctf.so")
 BILINEAR4, STF1, LIST, BOX, MASK = 0, 1, 2, 3, 4
 FB_STF1, FB_C, FB_CPLUS = 0, 1, 2
 FILTER_BILINEAR, FILTER_BSPLINE, FILTER_CATMULL_ROM = 0, 1, 2
+SPLIT_AUTO, SPLIT_OFF = 0, 1
 TEX_SINUSOIDS, TEX_AFFINE, TEX_CONSTANT, TEX_TABLE, TEX_DECODER = 0, 1, 2, 3, 4
 FP16, BF16 = 0, 1
 TILE_OK, TILE_CAP, TILE_OVERFLOW, TILE_EMPTY = 1, 2, 4, 8
@@ -52,7 +53,7 @@ class TextureDesc(ctypes.Structure):
 class Method(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("box_w", ctypes.c_int32), ("box_h", ctypes.c_int32),
                 ("mask_side", ctypes.c_int32), ("max_evals_per_lane", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("filter", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("filter", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class DecoderDesc(ctypes.Structure):
@@ -123,8 +124,9 @@ def _stream(stream) -> Optional[int]:
     return s.cuda_stream
 
 
-def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_BILINEAR) -> Method:
-    return Method(kind, box[0], box[1], mask_side, k, fallback, filter)
+def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_BILINEAR,
+           split=SPLIT_AUTO) -> Method:
+    return Method(kind, box[0], box[1], mask_side, k, fallback, filter, split)
 
 
 class Context:

@@ -238,6 +238,8 @@ static ctf_status check_method(const ctf_method* m, const char* who)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown fallback %d", who, m->fallback);
     if (m->filter < CTF_FILTER_BILINEAR || m->filter > CTF_FILTER_CATMULL_ROM)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown filter %d", who, m->filter);
+    if (m->split != CTF_SPLIT_AUTO && m->split != CTF_SPLIT_OFF)
+        return fail(CTF_ERR_INVALID_ARG, "%s: unknown split mode %d", who, m->split);
     return CTF_OK;
 }
 
@@ -259,6 +261,7 @@ static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int
     a.max_evals = m->max_evals_per_lane;
     a.fallback = m->fallback;
     a.filter = m->filter;
+    a.split = m->split;
     a.seed = seed;
     a.layer = 0;
     a.tile_stats = ts;

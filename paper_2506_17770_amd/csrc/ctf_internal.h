@@ -24,6 +24,7 @@ struct FilterArgs {
     int max_evals;
     int fallback;               // CTF_FB_* for the lanes of a failed wave
     int filter;                 // CTF_FILTER_*
+    int split;                  // CTF_SPLIT_*
     uint64_t seed;
     uint32_t layer;
     ctf_tile_stats* tile_stats;

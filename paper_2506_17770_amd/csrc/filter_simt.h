@@ -99,14 +99,30 @@ __device__ __forceinline__ int list_find(const WaveLds<F>& L, int n, uint64_t ke
     return lo;
 }
 
+// Split-texel production reads the procedural terms from LDS (a lane's
+// channel varies across the wave, so they cannot come through the scalar
+// cache); up to this many terms per channel are staged.
+constexpr int kSplitTerms = 64;
+
 template <int METHOD, int TEX, bool STATS, int FILTER>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterArgs a, DevTexture T)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
+    constexpr bool kCanSplit = (METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK) &&
+                               TEX == CTF_TEX_SINUSOIDS;
     __shared__ WaveLds<F> lds_all[kWavesPerBlock];
+    __shared__ int4 terms_lds[kCanSplit ? 4 * kSplitTerms : 1];
     const int wid = threadIdx.x / kWave;
     const int lane = lane_id();
     WaveLds<F>& L = lds_all[wid];
+    bool split_ok = false;
+    if constexpr (kCanSplit) {
+        split_ok = a.split == CTF_SPLIT_AUTO && T.n_terms <= kSplitTerms;
+        if (split_ok) {
+            for (int i = threadIdx.x; i < 4 * T.n_terms; i += blockDim.x) terms_lds[i] = T.terms[i];
+            __syncthreads();
+        }
+    }
     FrameCounters fc;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     for (TileWalk tw((int64_t)blockIdx.x * kWavesPerBlock + wid, nw, a.tiles_x); tw.tile < a.ntiles; tw.advance(nw)) {
@@ -270,35 +286,54 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
             wave_lds_sync();
             if (inA) res = fallback_color<FILTER>(L, P, f, pick, xmin, ymin);
         } else {
-            for (int round = 0; round < (kCollab ? k : 1); ++round) {
+            // texel of item i of the method's order
+            auto item_xy = [&](int item) -> int2 {
+                if constexpr (METHOD == CTF_BOX) {
+                    return make_int2(xmin + item % bbw, ymin + item / bbw);
+                } else {
+                    if (sorted) {
+                        const uint64_t key = L.keys[item];
+                        return make_int2(xmin + (int)(uint32_t)key, ymin + (int)(key >> 32));
+                    }
+                    const int t = L.items[item];
+                    return make_int2(xmin + (t & 15), ymin + (t >> 4));
+                }
+            };
+            auto list_out = [&](int item, int2 e) {
+                if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = e;
+            };
+            // split-texel production: a wave with n <= 32 (16) texels and no
+            // one-tap draws evaluates each texel on 2 (4) lanes, one channel
+            // pair (one channel) per lane, over all 64 lanes
+            bool split = false;
+            if constexpr (kCanSplit) {
+                split = split_ok && success && stfmask == 0 && n <= 32;
+                if (split) {
+                    const int ls = n <= 16 ? 2 : 1;    // log2 of lanes per texel
+                    const int item = lane >> ls, part = lane & ((1 << ls) - 1);
+                    if (item < n) {
+                        const int2 e = item_xy(item);
+                        if (part == 0) list_out(item, e);
+                        float* v = reinterpret_cast<float*>(&L.vals[item]);
+                        const int K = T.n_terms, nc = 4 >> ls, c0 = part * nc;
+                        const int xm = e.x & (int)T.wmask, ym = e.y & (int)T.wmask;
+                        v[c0] = sinusoid_channel(terms_lds + c0 * K, K, T.wmask, T.inv_w, xm, ym);
+                        if (nc == 2) v[c0 + 1] = sinusoid_channel(terms_lds + (c0 + 1) * K, K, T.wmask, T.inv_w, xm, ym);
+                    }
+                }
+            }
+            for (int round = 0; !split && round < (kCollab ? k : 1); ++round) {
                 const int item = rankA + round * nA;
                 const bool produce = kCollab && success && inA && item < n;
                 const bool draw_now = draws && round == 0;
                 if (ballot(produce || draw_now) == 0) break;
-                int ex = pick.x, ey = pick.y;
+                int2 e = pick;
                 if (produce) {
-                    if constexpr (METHOD == CTF_BOX) {
-                        ex = xmin + item % bbw;
-                        ey = ymin + item / bbw;
-                    } else {
-                        if (sorted) {
-                            const uint64_t key = L.keys[item];
-                            ex = xmin + (int)(uint32_t)key;
-                            ey = ymin + (int)(key >> 32);
-                        } else {
-                            const int t = L.items[item];
-                            ex = xmin + (t & 15);
-                            ey = ymin + (t >> 4);
-                        }
-                    }
-                    if (a.lists) {
-                        int32_t* e = a.lists + ((size_t)tile * kMaxItems + item) * 2;
-                        e[0] = ex;
-                        e[1] = ey;
-                    }
+                    e = item_xy(item);
+                    list_out(item, e);
                 }
                 if (produce || draw_now) {
-                    const float4 v = texel_eval<TEX>(T, ex, ey);
+                    const float4 v = texel_eval<TEX>(T, e.x, e.y);
                     if (produce) L.vals[item] = v;
                     if (draw_now) res = v;
                 }

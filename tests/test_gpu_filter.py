@@ -269,3 +269,22 @@ def test_1080p_four_planes_sampled_parity(G, c1, name, gk, ok, box, k):
                 n = o["stats"]["n"][t]
                 assert np.array_equal(g["lists"][t, :n], o["lists"][t, :n])
     tex.close()
+
+
+@pytest.mark.parametrize("name,gk,ok,box,k", [m for m in METHODS if m[1] >= 2])
+def test_split_texel_production_is_bitwise_identical(G, c0, name, gk, ok, box, k):
+    """Split-texel production (2 or 4 lanes per texel on small sets) gives
+    the same bits, lists and counts as one lane per texel."""
+    ctf, ctx, _ = G
+    sc, pqj, amp = c0
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    on = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_AUTO), seed=4)
+    off = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_OFF), seed=4)
+    st = on["stats"]
+    split_tiles = ((st["flags"] & O.TILE_OK) != 0) & (st["stf"] == 0) & (st["n"] <= 32)
+    assert split_tiles.sum() > 20
+    assert np.array_equal(on["out"], off["out"])
+    assert np.array_equal(on["lists"], off["lists"])
+    for f in STAT_FIELDS:
+        assert np.array_equal(on["stats"][f], off["stats"][f]), f
+    tex.close()
