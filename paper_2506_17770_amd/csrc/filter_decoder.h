@@ -133,21 +133,32 @@ __device__ __forceinline__ void finish_row(float4* vals, int R, int row, const F
 // Every prefetch is issued unconditionally (rows past R fetch cell 0), so
 // each path reaches the next tile's MLP with the same loads outstanding and
 // the wait before it covers only the current tile's gathers.
+// The same with the first tile's gathers already issued into fa.
+template <int P>
+__device__ __forceinline__ void decode_rows_from(const int2* rows, float4* vals, int R, LatentFetch& fa,
+                                                 const LatentGrid& G, const FwdWeights<P>& W, const Biases& Bz,
+                                                 int j, int g)
+{
+    const int T = (R + 15) >> 4;
+    if (T == 0) return;
+    LatentFetch fb;
+    for (int t = 0; t < T; t += 2) {
+        fetch_row<P>(rows, R, 16 * (t + 1) + j, G, g, fb);
+        finish_row<P>(vals, R, 16 * t + j, W, Bz, fa, g);
+        if (t + 1 >= T) break;
+        fetch_row<P>(rows, R, 16 * (t + 2) + j, G, g, fa);
+        finish_row<P>(vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& G, const FwdWeights<P>& W,
                                             const Biases& Bz, int j, int g)
 {
-    const int T = (R + 15) >> 4;
-    if (T == 0) return;
-    LatentFetch fa, fb;
+    if (R <= 0) return;
+    LatentFetch fa;
     fetch_row<P>(L.rows, R, j, G, g, fa);
-    for (int t = 0; t < T; t += 2) {
-        fetch_row<P>(L.rows, R, 16 * (t + 1) + j, G, g, fb);
-        finish_row<P>(L.vals, R, 16 * t + j, W, Bz, fa, g);
-        if (t + 1 >= T) break;
-        fetch_row<P>(L.rows, R, 16 * (t + 2) + j, G, g, fa);
-        finish_row<P>(L.vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
-    }
+    decode_rows_from<P>(L.rows, L.vals, R, fa, G, W, Bz, j, g);
 }
 
 __device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t tile, uint64_t act, uint64_t A,
