@@ -151,7 +151,11 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                     ("mask_fbCplus", ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS)),
                     ("list_k2", ctf.method(ctf.LIST, k=2)),
                     ("list_no_split", ctf.method(ctf.LIST, split=ctf.SPLIT_OFF)),
-                    ("mask_no_split", ctf.method(ctf.MASK, split=ctf.SPLIT_OFF))):
+                    ("mask_no_split", ctf.method(ctf.MASK, split=ctf.SPLIT_OFF)),
+                    ("bilinear4_8x4", ctf.method(ctf.BILINEAR4, wave_shape=ctf.WAVE_8X4)),
+                    ("list_8x4", ctf.method(ctf.LIST, wave_shape=ctf.WAVE_8X4)),
+                    ("box4x4_8x4", ctf.method(ctf.BOX, box=(4, 4), wave_shape=ctf.WAVE_8X4)),
+                    ("mask_8x4", ctf.method(ctf.MASK, wave_shape=ctf.WAVE_8X4))):
         fs = ctf.frame_stats_buffer()
         ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs)
         torch.cuda.synchronize()
@@ -167,7 +171,8 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
         v["speedup_vs_bilinear4"] = v["gpixels_per_s"] / b4
     tex.close()
     return {"workload": "1920x1080 four-plane frame, 2048^2 procedural texture (K=32 sinusoids "
-                        "per channel, F=64), per-lane texel production", "methods": res}
+                        "per channel, F=64), per-lane texel production; *_8x4: the paper's 8x4 tiles, "
+                        "two per wave64", "methods": res}
 
 
 def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):

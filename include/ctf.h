@@ -93,6 +93,14 @@ enum { CTF_FILTER_BILINEAR = 0, CTF_FILTER_BSPLINE = 1, CTF_FILTER_CATMULL_ROM =
  * 64 terms per channel).  Results are bit-identical either way. */
 enum { CTF_SPLIT_AUTO = 0, CTF_SPLIT_OFF = 1 };
 
+/* Wave shape.  CTF_WAVE_8X8: one 8x8-pixel tile per wave64 (lane = 8 ly + lx).
+ * CTF_WAVE_8X4: the paper's 8x4-pixel tiles of 32 lanes (Section 3), two per
+ * wave64, each half-wave taking its own collaborative step; tiles are then
+ * 8x4, numbered row-major over ceil(sw/8) x ceil(sh/4) (tile records and
+ * lists per 8x4 tile).  8x4 supports the bilinear filter, the one-tap
+ * fallback and the procedural / table producers. */
+enum { CTF_WAVE_8X8 = 0, CTF_WAVE_8X4 = 1 };
+
 /* Texel producers (Section 3: "produce a texel"). */
 enum {
     CTF_TEX_SINUSOIDS = 0,  /* procedural sum of sinusoids (below) */
@@ -173,6 +181,7 @@ typedef struct ctf_method {
     int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
     int32_t filter;              /* CTF_FILTER_*; ctf_filter_layers takes bilinear only */
     int32_t split;               /* CTF_SPLIT_AUTO / CTF_SPLIT_OFF (procedural textures) */
+    int32_t wave_shape;          /* CTF_WAVE_8X8 / CTF_WAVE_8X4 */
 } ctf_method;
 
 /* One record per tile (128 bytes). */

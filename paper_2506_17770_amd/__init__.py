@@ -24,6 +24,7 @@ BILINEAR4, STF1, LIST, BOX, MASK = 0, 1, 2, 3, 4
 FB_STF1, FB_C, FB_CPLUS = 0, 1, 2
 FILTER_BILINEAR, FILTER_BSPLINE, FILTER_CATMULL_ROM = 0, 1, 2
 SPLIT_AUTO, SPLIT_OFF = 0, 1
+WAVE_8X8, WAVE_8X4 = 0, 1
 TEX_SINUSOIDS, TEX_AFFINE, TEX_CONSTANT, TEX_TABLE, TEX_DECODER = 0, 1, 2, 3, 4
 FP16, BF16 = 0, 1
 TILE_OK, TILE_CAP, TILE_OVERFLOW, TILE_EMPTY = 1, 2, 4, 8
@@ -53,7 +54,8 @@ class TextureDesc(ctypes.Structure):
 class Method(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("box_w", ctypes.c_int32), ("box_h", ctypes.c_int32),
                 ("mask_side", ctypes.c_int32), ("max_evals_per_lane", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("filter", ctypes.c_int32), ("split", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("filter", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("wave_shape", ctypes.c_int32)]
 
 
 class DecoderDesc(ctypes.Structure):
@@ -125,8 +127,8 @@ def _stream(stream) -> Optional[int]:
 
 
 def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_BILINEAR,
-           split=SPLIT_AUTO) -> Method:
-    return Method(kind, box[0], box[1], mask_side, k, fallback, filter, split)
+           split=SPLIT_AUTO, wave_shape=WAVE_8X8) -> Method:
+    return Method(kind, box[0], box[1], mask_side, k, fallback, filter, split, wave_shape)
 
 
 class Context:
@@ -298,9 +300,9 @@ class Decoder:
             self.handle = None
 
 
-def tile_stats_buffer(sw, sh, device="cuda"):
+def tile_stats_buffer(sw, sh, device="cuda", tile_h=8):
     import torch
-    tiles = ((sw + 7) // 8) * ((sh + 7) // 8)
+    tiles = ((sw + 7) // 8) * ((sh + tile_h - 1) // tile_h)
     return torch.zeros((tiles, TILE_STATS_DTYPE.itemsize), dtype=torch.uint8, device=device)
 
 
@@ -318,9 +320,9 @@ def frame_stats_dict(buf) -> dict:
     return {k: int(v[i]) for i, k in enumerate(FRAME_STATS_FIELDS)}
 
 
-def lists_buffer(sw, sh, device="cuda"):
+def lists_buffer(sw, sh, device="cuda", tile_h=8):
     import torch
-    tiles = ((sw + 7) // 8) * ((sh + 7) // 8)
+    tiles = ((sw + 7) // 8) * ((sh + tile_h - 1) // tile_h)
     return torch.full((tiles, MAX_ITEMS, 2), -2**31, dtype=torch.int32, device=device)
 
 

@@ -240,6 +240,10 @@ static ctf_status check_method(const ctf_method* m, const char* who)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown filter %d", who, m->filter);
     if (m->split != CTF_SPLIT_AUTO && m->split != CTF_SPLIT_OFF)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown split mode %d", who, m->split);
+    if (m->wave_shape != CTF_WAVE_8X8 && m->wave_shape != CTF_WAVE_8X4)
+        return fail(CTF_ERR_INVALID_ARG, "%s: unknown wave shape %d", who, m->wave_shape);
+    if (m->wave_shape == CTF_WAVE_8X4 && (m->filter != CTF_FILTER_BILINEAR || m->fallback != CTF_FB_STF1))
+        return fail(CTF_ERR_UNSUPPORTED, "%s: 8x4 waves take the bilinear filter and the one-tap fallback", who);
     return CTF_OK;
 }
 
@@ -253,8 +257,9 @@ static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int
     a.out = out;
     a.sw = sw;
     a.sh = sh;
+    const int tile_h = m->wave_shape == CTF_WAVE_8X4 ? 4 : kTile;
     a.tiles_x = (sw + kTile - 1) / kTile;
-    a.ntiles = (int64_t)a.tiles_x * ((sh + kTile - 1) / kTile);
+    a.ntiles = (int64_t)a.tiles_x * ((sh + tile_h - 1) / tile_h);
     a.method = m->kind;
     a.box_w = m->box_w;
     a.box_h = m->box_h;
@@ -262,6 +267,7 @@ static FilterArgs filter_args(const float* uv, const float* duv, int32_t sw, int
     a.fallback = m->fallback;
     a.filter = m->filter;
     a.split = m->split;
+    a.wave_shape = m->wave_shape;
     a.seed = seed;
     a.layer = 0;
     a.tile_stats = ts;
@@ -285,6 +291,8 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_d
     if (st != CTF_OK) return st;
     if (m->filter != CTF_FILTER_BILINEAR)
         return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the layered launch takes the bilinear filter only");
+    if (m->wave_shape != CTF_WAVE_8X8)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the layered launch takes 8x8 waves only");
     for (int l = 0; l < n_layers; ++l) {
         if (!texs[l] || texs[l]->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: texture %d", l);
         if (texs[l]->dev.kind != CTF_TEX_DECODER || texs[l]->dec.precision != texs[0]->dec.precision)
@@ -319,8 +327,12 @@ ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, 
     const FilterArgs a = filter_args(uv, uv_derivs, sw, sh, m, seed, out, tile_stats, frame_stats, debug_lists,
                                      debug_stf);
     hipError_t e;
+    if (m->wave_shape == CTF_WAVE_8X4 && tex->dev.kind == CTF_TEX_DECODER)
+        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: 8x4 waves take the procedural and table producers");
     if (tex->dev.kind == CTF_TEX_DECODER)
         e = ctf_internal_decoder_filter(tex, a, (hipStream_t)stream);
+    else if (m->wave_shape == CTF_WAVE_8X4)
+        e = launch_filter_w32(a, tex->dev, (hipStream_t)stream);
     else
         e = launch_filter_simt(a, tex->dev, (hipStream_t)stream);
     if (e == hipErrorInvalidValue) return fail(CTF_ERR_UNSUPPORTED, "ctf_filter: combination not built");

@@ -25,6 +25,7 @@ struct FilterArgs {
     int fallback;               // CTF_FB_* for the lanes of a failed wave
     int filter;                 // CTF_FILTER_*
     int split;                  // CTF_SPLIT_*
+    int wave_shape;             // CTF_WAVE_*
     uint64_t seed;
     uint32_t layer;
     ctf_tile_stats* tile_stats;
@@ -44,6 +45,7 @@ struct DevDecoderWeights {
 
 hipError_t launch_filter_simt(const FilterArgs& a, const DevTexture& T, hipStream_t s);
 hipError_t launch_filter_simt_cubic(const FilterArgs& a, const DevTexture& T, hipStream_t s);
+hipError_t launch_filter_w32(const FilterArgs& a, const DevTexture& T, hipStream_t s);
 hipError_t launch_texel_eval_simt(const DevTexture& T, const int32_t* xy, int64_t n, float* out,
                                   hipStream_t s);
 
