@@ -24,6 +24,10 @@ constexpr float kRange = 16777216.0f; // |texel position| < 2^24
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Index of this wave in its workgroup, as a wave-uniform (scalar) value so
+// that everything derived from it (tile walks, layer loops) stays scalar.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // number of set bits of m below this lane (rank of the lane in m)

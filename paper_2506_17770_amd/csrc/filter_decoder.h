@@ -508,7 +508,7 @@ __global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>
     FilterArgs a, DevDecoderWeights D)
 {
     __shared__ DecLds lds_all[kDecWaves];
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_in_block();
     const int lane = lane_id();
     DecLds& L = lds_all[wid];
     FwdWeights<P> W;

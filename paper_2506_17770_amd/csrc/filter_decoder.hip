@@ -25,10 +25,11 @@ struct LayerSet {
 };
 
 template <int METHOD, int P, bool STATS, bool FB>
-__global__ __launch_bounds__(64 * kDecWaves, 2) void k_filter_layers(FilterArgs a, LayerSet LS)
+__global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, CTF_FILTER_BILINEAR>())) void
+k_filter_layers(FilterArgs a, LayerSet LS)
 {
     __shared__ DecLds lds_all[kDecWaves];
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_in_block();
     const int lane = lane_id();
     DecLds& L = lds_all[wid];
     const Band band(a.ntiles, wid);

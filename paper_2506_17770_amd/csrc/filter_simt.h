@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                                TEX == CTF_TEX_SINUSOIDS;
     __shared__ WaveLds<F> lds_all[kWavesPerBlock];
     __shared__ int4 terms_lds[kCanSplit ? 4 * kSplitTerms : 1];
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_in_block();
     const int lane = lane_id();
     WaveLds<F>& L = lds_all[wid];
     bool split_ok = false;

@@ -108,7 +108,7 @@ template <int METHOD, int TEX, bool STATS>
 __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, DevTexture T)
 {
     __shared__ W32Lds lds_all[kW32Waves];
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_in_block();
     const int lane = lane_id();
     const int h = lane >> 5, ll = lane & 31;
     W32Lds& L = lds_all[wid];
