@@ -206,19 +206,38 @@ __global__ void k_fx_to_float(const int64_t* __restrict__ fx, int64_t n, float* 
         out[i] = (float)fx[i] * kFxInv;
 }
 
+__device__ __forceinline__ int2 sample_xy(uint64_t seed, uint32_t step, int i, int tex_w)
+{
+    const uint32_t base = pcg_hash((uint32_t)step ^
+                                   pcg_hash((uint32_t)(seed >> 32) ^ pcg_hash((uint32_t)seed)));
+    const uint32_t h = pcg_hash((uint32_t)i ^ base);
+    return make_int2((int)(h & (uint32_t)(tex_w - 1)), (int)(pcg_hash(h) & (uint32_t)(tex_w - 1)));
+}
+
 template <int TEX>
 __global__ void k_sample(DevTexture T, uint64_t seed, uint32_t step, int batch, int tex_w,
                          int2* __restrict__ xy, float4* __restrict__ target)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= batch) return;
-    const uint32_t base = pcg_hash((uint32_t)step ^
-                                   pcg_hash((uint32_t)(seed >> 32) ^ pcg_hash((uint32_t)seed)));
-    const uint32_t h = pcg_hash((uint32_t)i ^ base);
-    const int x = (int)(h & (uint32_t)(tex_w - 1));
-    const int y = (int)(pcg_hash(h) & (uint32_t)(tex_w - 1));
-    xy[i] = make_int2(x, y);
-    target[i] = texel_eval<TEX>(T, x, y);
+    const int2 p = sample_xy(seed, step, i, tex_w);
+    xy[i] = p;
+    target[i] = texel_eval<TEX>(T, p.x, p.y);
+}
+
+// Procedural targets one channel per thread (channel = blockIdx.y, so the
+// terms come through the scalar cache): four times the threads of k_sample
+// for the same values.
+__global__ void k_sample_sinusoid(DevTexture T, uint64_t seed, uint32_t step, int batch, int tex_w,
+                                  int2* __restrict__ xy, float* __restrict__ target)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch) return;
+    const int c = blockIdx.y;
+    const int2 p = sample_xy(seed, step, i, tex_w);
+    if (c == 0) xy[i] = p;
+    const int xm = p.x & (int)T.wmask, ym = p.y & (int)T.wmask;
+    target[4 * (int64_t)i + c] = sinusoid_channel(T.terms + c * T.n_terms, T.n_terms, T.wmask, T.inv_w, xm, ym);
 }
 
 struct TrainArgs {
@@ -500,7 +519,7 @@ struct AdamArgs {
     float* m;
     float* v;
     const float* grad;        // MLP part (p >= mlp0)
-    const int64_t* glat_fx;   // latent part, fixed point
+    int64_t* glat_fx;   // latent part, fixed point
     int64_t total, mlp0;
     int hidden;
     float lr, b1, b2, eps, bc1, bc2;  // bias corrections 1 - beta^t
@@ -516,7 +535,13 @@ __global__ void k_adam(AdamArgs a)
     if (p >= a.total) return;
     float th = a.master[p];
     if (UPDATE) {
-        const float gr = p < a.mlp0 ? (float)a.glat_fx[p] * kFxInv : a.grad[p];
+        float gr;
+        if (p < a.mlp0) {
+            gr = (float)a.glat_fx[p] * kFxInv;
+            a.glat_fx[p] = 0;   // ready for the next step's sums
+        } else {
+            gr = a.grad[p];
+        }
         const float m = __builtin_fmaf(a.b1, a.m[p], (1.f - a.b1) * gr);
         const float v = __builtin_fmaf(a.b2, a.v[p], (1.f - a.b2) * gr * gr);
         a.m[p] = m;
@@ -654,13 +679,15 @@ hipError_t ensure_lp(ctf_decoder d, int precision, hipStream_t s)
 // Loss and gradient of a batch: the MLP part lands in grad[mlp0..]; the
 // latent part in d->glat_fx (fixed point), copied to grad[0..mlp0) as float
 // when latent_to_grad is set (training reads the fixed-point sums directly).
+// zero_latent clears the fixed-point sums first; the training loop clears
+// them once and then relies on the Adam step, which zeroes what it reads.
 template <int P>
 hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target, int32_t n,
-                          float* loss, float* grad, bool latent_to_grad, hipStream_t s)
+                          float* loss, float* grad, bool latent_to_grad, bool zero_latent, hipStream_t s)
 {
     const Layout& L = d->lay;
     const int fb = 1024;
-    hipLaunchKernelGGL(k_zero64, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0);
+    if (zero_latent) hipLaunchKernelGGL(k_zero64, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0);
     TrainArgs a;
     a.grid = latent_grid(d->desc, d->lat_lp);
     a.w = d->w_lp;
@@ -832,8 +859,8 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder d, const int32_t* xy, const float* 
     hipError_t e = ensure_batch(d, n);
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
     if (e == hipSuccess)
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, s)
-                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, s);
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, true, s)
+                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, true, s);
     return e == hipSuccess ? CTF_OK : hip_fail(e, "ctf_decoder_loss_grad");
 }
 
@@ -855,6 +882,7 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
     if (e != hipSuccess) return hip_fail(e, "ctf_decoder_train: setup");
     const int sb = 256;
+    if (steps > 0) hipLaunchKernelGGL(k_zero64, dim3(1024), dim3(256), 0, s, d->glat_fx, d->lay.mlp0);
     for (int64_t it = 0; it < steps && e == hipSuccess; ++it) {
         const dim3 sg((unsigned)((batch + sb - 1) / sb));
         int2* xy = reinterpret_cast<int2*>(d->xy);
@@ -862,7 +890,8 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
         const uint32_t st = (uint32_t)d->step;
         switch (T.kind) {
         case CTF_TEX_SINUSOIDS:
-            hipLaunchKernelGGL(k_sample<CTF_TEX_SINUSOIDS>, sg, dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy, tg);
+            hipLaunchKernelGGL(k_sample_sinusoid, dim3(sg.x, 4), dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy,
+                               reinterpret_cast<float*>(tg));
             break;
         case CTF_TEX_AFFINE:
             hipLaunchKernelGGL(k_sample<CTF_TEX_AFFINE>, sg, dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy, tg);
@@ -874,8 +903,8 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
             hipLaunchKernelGGL(k_sample<CTF_TEX_TABLE>, sg, dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy, tg);
         }
         float* lt = loss_trace ? loss_trace + it : d->loss_tmp;
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, false, s)
-                                  : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, false, s);
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, false, false, s)
+                                  : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, false, false, s);
         if (e != hipSuccess) break;
         d->step += 1;
         e = precision == CTF_BF16 ? launch_adam<CTF_BF16, true>(d, lr, s) : launch_adam<CTF_FP16, true>(d, lr, s);
