@@ -536,6 +536,312 @@ __global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
 
+// ---------------------------------------------------------------------------
+// Batched decode (bilinear filter, no C / C+ fallback).  A wave plans each
+// tile into a staging row list, then appends the rows to the decode batch;
+// the batch of up to two tiles (at most 256 rows) is decoded in one pass, so
+// a tile's few rows share the pass's start-up and its partial last MFMA
+// tile with its neighbour.  A planned tile's per-lane state waits in LDS
+// until its gather, so no two tiles' state is live in registers.
+// ---------------------------------------------------------------------------
+
+struct LaneState {
+    float s, t;       // footprint position
+    uint32_t idx;     // gi | gd << 16: tap (i, j) at item gi + i + gd j (via the rank table for Mask/List)
+    uint32_t misc;    // draw_row | exact << 8 | draws << 9 | in_screen << 10
+};
+
+struct BatchLds {
+    DecLds L;                   // vals, rows (the batch), keys (sort keys, then the staging rows), rank (slot 0), bytes
+    uint8_t rank1[256];         // rank table of slot 1
+    LaneState st[2][kWave];     // per-lane state by slot
+};
+
+struct Pending {
+    int64_t tile;
+    int tx, ty;
+    int base;                   // first row of the tile in the batch
+};
+
+// Plan one tile: decisions, staging rows (L.keys as int2), the rank table
+// and per-lane state of `slot`, debug outputs, tile record and counters.
+// Returns the tile's row count.
+template <int METHOD, bool STATS>
+__device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int slot, int64_t tile, int tx, int ty,
+                                         const Footprint& f, FrameCounters& fc)
+{
+    DecLds& L = BL.L;
+    int2* const stage = reinterpret_cast<int2*>(L.keys);
+    uint8_t* const rank = slot ? BL.rank1 : L.rank;
+    const int lane = lane_id();
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    const bool in_screen = px < a.sw && py < a.sh;
+    const int64_t pix = (int64_t)py * a.sw + px;
+    const bool inA = f.active && f.magnify;
+    const uint64_t act = ballot(f.active);
+    const uint64_t A = ballot(inA);
+    const int nA = popc64(A);
+
+    int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
+    constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    if ((kCollab || STATS) && nA > 0) {
+        xmin = wave_min(inA ? f.x0 : INT32_MAX);
+        ymin = wave_min(inA ? f.y0 : INT32_MAX);
+        bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
+        bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
+    }
+    const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+
+    uint64_t B[4] = {0, 0, 0, 0};
+    int nmask = 0;
+    constexpr bool kNeedMask = METHOD == CTF_MASK || METHOD == CTF_LIST || STATS;
+    if (kNeedMask && fits16) {
+        reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
+        wave_lds_sync();
+        if (inA) L.bytes[16 * (f.y0 - ymin) + (f.x0 - xmin)] = 1;
+        wave_lds_sync();
+        uint64_t C[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) C[w] = ballot(L.bytes[64 * w + lane] != 0);
+        footprint_mask(C, B);
+        nmask = popc64(B[0]) + popc64(B[1]) + popc64(B[2]) + popc64(B[3]);
+    }
+
+    const int k = a.max_evals;
+    int n = 0;
+    bool cap_ok = true, count_ok = true, success = false, sorted = false;
+    int unique = nmask;
+    if constexpr (METHOD == CTF_BOX) {
+        const int64_t area = (int64_t)bbw * bbh;
+        n = area > INT32_MAX ? INT32_MAX : (int)area;
+        cap_ok = (a.box_w == 0 || bbw <= a.box_w) && (a.box_h == 0 || bbh <= a.box_h);
+        count_ok = area <= (int64_t)k * nA;
+        success = nA > 0 && cap_ok && count_ok;
+    } else if constexpr (METHOD == CTF_MASK) {
+        cap_ok = fits16;
+        n = fits16 ? nmask : 0;
+        count_ok = n <= k * nA;
+        success = fits16 && count_ok;
+    } else if constexpr (METHOD == CTF_LIST) {
+        if (nA > 0 && !fits16) {
+            n = dec_list_sorted<2>(L, inA, f.x0, f.y0, xmin, ymin);
+            sorted = true;
+        } else {
+            n = nmask;
+        }
+        unique = n;
+        count_ok = n <= k * nA;
+        success = nA > 0 && count_ok;
+    }
+    if constexpr (STATS && METHOD != CTF_LIST) {
+        if (nA > 0 && !fits16) unique = dec_list_sorted<2>(L, inA, f.x0, f.y0, xmin, ymin);
+    }
+    if (nA == 0) unique = 0;
+
+    bool exact, draws;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        exact = f.active;
+        draws = false;
+    } else if constexpr (METHOD == CTF_STF1) {
+        exact = false;
+        draws = f.active;
+    } else {
+        exact = inA && success;
+        draws = f.active && !exact;
+    }
+    const uint64_t stfmask = ballot(draws);
+    const int nstf = popc64(stfmask);
+    int2 pick = make_int2(INT32_MIN, INT32_MIN);
+    if (draws) {
+        uint32_t h1, h2;
+        stf_hashes(a.seed, a.layer, px, py, h1, h2);
+        pick = stf_pick_h(f, h1, h2);
+    }
+
+    // staging rows (in the keys array) and the inverse table of Mask/List
+    const int rank_act = mbcnt(act);
+    const int ns = success ? n : 0;
+    int R;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        R = 4 * popc64(act);
+        if (f.active) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) stage[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
+        }
+    } else {
+        R = ns + nstf;
+        if (success) {
+            if (sorted) {
+                // the lane's item indices first (they read the sorted keys),
+                // then the keys become staging rows in place
+                if (inA) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
+                                             (uint32_t)(f.x0 + (q & 1) - xmin);
+                        rank[4 * lane + q] = (uint8_t)dec_list_find(L.keys, n, key);
+                    }
+                }
+                wave_lds_sync();
+            }
+            if (METHOD == CTF_BOX || sorted) {
+                for (int i = lane; i < ns; i += kWave) {
+                    int ex, ey;
+                    if (METHOD == CTF_BOX) {
+                        ex = xmin + i % bbw;
+                        ey = ymin + i / bbw;
+                    } else {
+                        const uint64_t key = L.keys[i];
+                        ex = xmin + (int)(uint32_t)key;
+                        ey = ymin + (int)(key >> 32);
+                    }
+                    stage[i] = make_int2(ex, ey);
+                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+                }
+            } else {
+                int base = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if ((B[w] >> lane) & 1u) {
+                        const int r = base + mbcnt(B[w]);
+                        const int t = 64 * w + lane;
+                        const int2 c = make_int2(xmin + (t & 15), ymin + (t >> 4));
+                        rank[t] = (uint8_t)r;
+                        stage[r] = c;
+                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
+                    }
+                    base += popc64(B[w]);
+                }
+            }
+        }
+        if (draws) stage[ns + mbcnt(stfmask)] = pick;
+    }
+    if (in_screen && a.stf_xy)
+        reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+    int gi = 0, gd = 0;
+    if constexpr (METHOD == CTF_BILINEAR4) {
+        gi = 4 * rank_act;
+        gd = 2;
+    } else if constexpr (METHOD == CTF_BOX) {
+        gi = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
+        gd = bbw;
+    } else if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
+        gi = sorted ? 4 * lane : 16 * (f.y0 - ymin) + (f.x0 - xmin);
+        gd = sorted ? 2 : 16;
+    }
+    LaneState ls;
+    ls.s = f.s;
+    ls.t = f.t;
+    ls.idx = (uint32_t)(gi & 0xffff) | ((uint32_t)(gd & 0xffff) << 16);
+    ls.misc = (uint32_t)((ns + mbcnt(stfmask)) & 0xff) | (exact ? 1u << 8 : 0u) | (draws ? 1u << 9 : 0u) |
+              (in_screen ? 1u << 10 : 0u);
+    BL.st[slot][lane] = ls;
+    if (lane == 0 && a.tile_stats)
+        write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, R, success, cap_ok,
+                         count_ok, nA);
+    if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), 0, kCollab && success, kCollab && nA && !success);
+    return R;
+}
+
+// Gather and weight a decoded tile from its per-lane state.
+template <int METHOD>
+__device__ __forceinline__ void gather_tile(const FilterArgs& a, BatchLds& BL, int slot, const Pending& pd)
+{
+    const int lane = lane_id();
+    const LaneState ls = BL.st[slot][lane];
+    const uint8_t* const rank = slot ? BL.rank1 : BL.L.rank;
+    const float4* const vals = BL.L.vals + pd.base;
+    const int gi = (int)(ls.idx & 0xffff), gd = (int)(ls.idx >> 16);
+    const bool exact = (ls.misc >> 8) & 1u, draws = (ls.misc >> 9) & 1u, in_screen = (ls.misc >> 10) & 1u;
+    float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (draws) res = vals[ls.misc & 0xff];
+    if (exact) {
+        int idx[4] = {gi, gi + 1, gi + gd, gi + gd + 1};
+        if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) idx[q] = rank[idx[q]];
+        }
+        res = bilerp(ls.s, ls.t, vals[idx[0]], vals[idx[1]], vals[idx[2]], vals[idx[3]]);
+    }
+    if (in_screen) {
+        const int px = pd.tx * kTile + (lane & 7), py = pd.ty * kTile + (lane >> 3);
+        reinterpret_cast<float4*>(a.out)[(int64_t)py * a.sw + px] = res;
+    }
+}
+
+template <int METHOD, int P, bool STATS>
+__global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterArgs a, DevDecoderWeights D)
+{
+    __shared__ BatchLds lds_all[kDecWaves];
+    const int wid = wave_in_block();
+    const int lane = lane_id();
+    const int j = lane & 15, g = lane >> 4;
+    BatchLds& BL = lds_all[wid];
+    FwdWeights<P> W;
+    W.load(D.w, lane);
+    Biases Bz;
+    Bz.load(D.bias, lane);
+    const float tex_w = (float)D.grid.tex_w;
+    const Band band(a.ntiles, wid);
+    FrameCounters fc;
+
+    Pending p0{}, p1{};   // the batch's tiles, slot 0 and slot 1 (named: no indexed private array)
+    int npend = 0, rows = 0;
+    // decode the batch, gather its tiles in order (slot = position)
+    auto flush = [&]() {
+        wave_lds_sync();
+        decode_rows<P>(BL.L, rows, D.grid, W, Bz, j, g);
+        wave_lds_sync();
+        gather_tile<METHOD>(a, BL, 0, p0);
+        if (npend == 2) gather_tile<METHOD>(a, BL, 1, p1);
+        fc.rows += (uint64_t)((rows + 15) & ~15);
+        npend = 0;
+        rows = 0;
+        wave_lds_sync();
+    };
+
+    float2 uv_next;
+    float4 d_next;
+    TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+    load_tile_px(a, next, band.end, uv_next, d_next);
+    while (next.tile < band.end) {
+        const TileWalk cur = next;
+        const float2 uv = uv_next;
+        const float4 d = d_next;
+        next.advance(band.nw);
+        load_tile_px(a, next, band.end, uv_next, d_next);
+        const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
+        // a full batch is decoded before the next tile's plan reuses a slot
+        if (npend == 2) flush();
+        const int R = plan_tile<METHOD, STATS>(a, BL, npend, cur.tile, cur.tx, cur.ty, f, fc);
+        if (rows + R > kMaxItems) {
+            // the rows do not fit behind the batch: decode it first.  The new
+            // tile was planned into slot npend; move its state and table to
+            // slot 0 when that changes.
+            const int s0 = npend;
+            flush();
+            if (s0 == 1) {
+                BL.st[0][lane] = BL.st[1][lane];
+                reinterpret_cast<uint32_t*>(BL.L.rank)[lane] = reinterpret_cast<const uint32_t*>(BL.rank1)[lane];
+                wave_lds_sync();
+            }
+        }
+        wave_lds_sync();
+        const int2* stage = reinterpret_cast<const int2*>(BL.L.keys);
+        for (int i = lane; i < R; i += kWave) BL.L.rows[rows + i] = stage[i];
+        wave_lds_sync();   // the next plan rewrites the staging rows
+        Pending& pd = npend ? p1 : p0;
+        pd.tile = cur.tile;
+        pd.tx = cur.tx;
+        pd.ty = cur.ty;
+        pd.base = rows;
+        ++npend;
+        rows += R;
+    }
+    if (npend) flush();
+    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
+}
+
 inline int device_cus()
 {
     int dev = 0, cus = 256;
@@ -579,9 +885,16 @@ struct GoFilter {
         static hipError_t run(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
         {
             const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
-            auto k = k_filter_dec<METHOD, P, STATS, FB, FILTER>;
-            const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
-            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+            if constexpr (FILTER == CTF_FILTER_BILINEAR && !FB && METHOD != CTF_BILINEAR4) {
+                // (the 4-tap filter's full tiles of 256 rows never share a batch)
+                auto k = k_filter_dec_batch<METHOD, P, STATS>;
+                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+                hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+            } else {
+                auto k = k_filter_dec<METHOD, P, STATS, FB, FILTER>;
+                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+                hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
+            }
             return hipGetLastError();
         }
     };
