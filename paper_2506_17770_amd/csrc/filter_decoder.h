@@ -769,13 +769,65 @@ __device__ __forceinline__ void gather_tile(const FilterArgs& a, BatchLds& BL, i
     }
 }
 
+// The batch of planned tiles of one wave (slots 0 and 1, named so that no
+// private array is indexed at run time).
+struct Batch {
+    Pending p0{}, p1{};
+    int npend = 0, rows = 0;
+};
+
+// Decode the batch and gather its tiles in slot order.
+template <int METHOD, int P>
+__device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, Batch& bt, const LatentGrid& G,
+                                            const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc)
+{
+    const int lane = lane_id();
+    wave_lds_sync();
+    decode_rows<P>(BL.L, bt.rows, G, W, Bz, lane & 15, lane >> 4);
+    wave_lds_sync();
+    if (bt.npend >= 1) gather_tile<METHOD>(a, BL, 0, bt.p0);
+    if (bt.npend == 2) gather_tile<METHOD>(a, BL, 1, bt.p1);
+    fc.rows += (uint64_t)((bt.rows + 15) & ~15);
+    bt.npend = 0;
+    bt.rows = 0;
+    wave_lds_sync();
+}
+
+// Plan a tile and append its rows to the batch (decoding the batch first
+// when it is full or the rows do not fit behind it).
+template <int METHOD, int P, bool STATS>
+__device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Batch& bt, const LatentGrid& G,
+                                          const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc,
+                                          const TileWalk& cur, const Footprint& f)
+{
+    const int lane = lane_id();
+    if (bt.npend == 2) batch_flush<METHOD, P>(a, BL, bt, G, W, Bz, fc);
+    const int R = plan_tile<METHOD, STATS>(a, BL, bt.npend, cur.tile, cur.tx, cur.ty, f, fc);
+    if (bt.rows + R > kMaxItems) {
+        // planned into slot 1: decode slot 0, then move the state and table
+        batch_flush<METHOD, P>(a, BL, bt, G, W, Bz, fc);
+        BL.st[0][lane] = BL.st[1][lane];
+        reinterpret_cast<uint32_t*>(BL.L.rank)[lane] = reinterpret_cast<const uint32_t*>(BL.rank1)[lane];
+    }
+    wave_lds_sync();
+    const int2* stage = reinterpret_cast<const int2*>(BL.L.keys);
+    for (int i = lane; i < R; i += kWave) BL.L.rows[bt.rows + i] = stage[i];
+    wave_lds_sync();   // the next plan rewrites the staging rows
+    Pending& pd = bt.npend ? bt.p1 : bt.p0;
+    pd.tile = cur.tile;
+    pd.tx = cur.tx;
+    pd.ty = cur.ty;
+    pd.base = bt.rows;
+    ++bt.npend;
+    bt.rows += R;
+}
+
 template <int METHOD, int P, bool STATS>
 __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterArgs a, DevDecoderWeights D)
 {
     __shared__ BatchLds lds_all[kDecWaves];
     const int wid = wave_in_block();
     const int lane = lane_id();
-    const int j = lane & 15, g = lane >> 4;
     BatchLds& BL = lds_all[wid];
     FwdWeights<P> W;
     W.load(D.w, lane);
@@ -784,22 +836,7 @@ __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterAr
     const float tex_w = (float)D.grid.tex_w;
     const Band band(a.ntiles, wid);
     FrameCounters fc;
-
-    Pending p0{}, p1{};   // the batch's tiles, slot 0 and slot 1 (named: no indexed private array)
-    int npend = 0, rows = 0;
-    // decode the batch, gather its tiles in order (slot = position)
-    auto flush = [&]() {
-        wave_lds_sync();
-        decode_rows<P>(BL.L, rows, D.grid, W, Bz, j, g);
-        wave_lds_sync();
-        gather_tile<METHOD>(a, BL, 0, p0);
-        if (npend == 2) gather_tile<METHOD>(a, BL, 1, p1);
-        fc.rows += (uint64_t)((rows + 15) & ~15);
-        npend = 0;
-        rows = 0;
-        wave_lds_sync();
-    };
-
+    Batch bt;
     float2 uv_next;
     float4 d_next;
     TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
@@ -811,34 +848,9 @@ __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterAr
         next.advance(band.nw);
         load_tile_px(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
-        // a full batch is decoded before the next tile's plan reuses a slot
-        if (npend == 2) flush();
-        const int R = plan_tile<METHOD, STATS>(a, BL, npend, cur.tile, cur.tx, cur.ty, f, fc);
-        if (rows + R > kMaxItems) {
-            // the rows do not fit behind the batch: decode it first.  The new
-            // tile was planned into slot npend; move its state and table to
-            // slot 0 when that changes.
-            const int s0 = npend;
-            flush();
-            if (s0 == 1) {
-                BL.st[0][lane] = BL.st[1][lane];
-                reinterpret_cast<uint32_t*>(BL.L.rank)[lane] = reinterpret_cast<const uint32_t*>(BL.rank1)[lane];
-                wave_lds_sync();
-            }
-        }
-        wave_lds_sync();
-        const int2* stage = reinterpret_cast<const int2*>(BL.L.keys);
-        for (int i = lane; i < R; i += kWave) BL.L.rows[rows + i] = stage[i];
-        wave_lds_sync();   // the next plan rewrites the staging rows
-        Pending& pd = npend ? p1 : p0;
-        pd.tile = cur.tile;
-        pd.tx = cur.tx;
-        pd.ty = cur.ty;
-        pd.base = rows;
-        ++npend;
-        rows += R;
+        batch_add<METHOD, P, STATS>(a, BL, bt, D.grid, W, Bz, fc, cur, f);
     }
-    if (npend) flush();
+    if (bt.npend) batch_flush<METHOD, P>(a, BL, bt, D.grid, W, Bz, fc);
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
 
