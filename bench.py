@@ -329,7 +329,7 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP16_TFLOPS, "traffic": measured_traffic(),
             "algorithmic_bytes": npx * 40,
-            "kernel": "k_filter_dec<LIST>", "work_per_launch": f"{s_col['evals']} decoded texels x {MLP_FLOP} FLOP"}
+            "kernel": "k_filter_dec_batch<LIST>", "work_per_launch": f"{s_col['evals']} decoded texels x {MLP_FLOP} FLOP"}
     achieved_b4 = s_b4["evals"] * MLP_FLOP / (ms_b4 * 1e-3) / 1e12
 
     res = {
