@@ -37,7 +37,7 @@ struct FilterArgs {
 // Decoder parameters in the layouts the MFMA kernels read (built once per
 // texture from the float32 master copy; see decoder_mlp.h).
 struct DevDecoderWeights {
-    LatentGrid grid;             // latents, 16-bit, both levels
+    InferGrid grid;              // latents, 16-bit, both levels, padded inference layout
     int precision;               // CTF_FP16 / CTF_BF16
     const uint16_t* w;           // packed A-operand weight blocks
     const float* bias;           // packed C-operand biases

@@ -607,6 +607,35 @@ LatentGrid latent_grid(const ctf_decoder_desc& d, const uint16_t* base)
     return G;
 }
 
+// The inference copy of the latents (see InferGrid): each level padded to
+// (L+1) x (L+1) cells by repeating its first row and column.
+InferGrid infer_grid(const ctf_decoder_desc& d, const uint16_t* base)
+{
+    InferGrid G;
+    G.base = base;
+    G.lvl1 = (uint32_t)((size_t)(d.l0 + 1) * (d.l0 + 1) * 16);
+    G.log_l0 = ilog2(d.l0);
+    G.log_l1 = ilog2(d.l1);
+    G.shift0 = ilog2(d.tex_w / d.l0);
+    G.shift1 = ilog2(d.tex_w / d.l1);
+    G.tex_w = d.tex_w;
+    return G;
+}
+
+std::vector<uint16_t> pad_latents(const std::vector<uint16_t>& lat, const ctf_decoder_desc& d)
+{
+    constexpr int C = 8;
+    std::vector<uint16_t> out((size_t)((d.l0 + 1) * (d.l0 + 1) + (d.l1 + 1) * (d.l1 + 1)) * C);
+    size_t src = 0, dst = 0;
+    for (int L : {d.l0, d.l1}) {
+        for (int i = 0; i <= L; ++i)
+            for (int j = 0; j <= L; ++j, dst += C)
+                for (int c = 0; c < C; ++c) out[dst + c] = lat[src + ((size_t)(i % L) * L + (j % L)) * C + c];
+        src += (size_t)L * L * C;
+    }
+    return out;
+}
+
 int train_waves(int n)
 {
     const int tiles = (n + 15) / 16;
@@ -931,6 +960,7 @@ ctf_status ctf_internal_decoder_texture(ctf_texture t)
     std::vector<uint16_t> lat, w;
     std::vector<float> bias;
     pack_host(P.data(), d->desc, prec, lat, w, bias);
+    lat = pad_latents(lat, d->desc);
     const size_t lat_b = lat.size() * 2, w_b = w.size() * 2, b_b = bias.size() * 4;
     const size_t o_w = (lat_b + 255) / 256 * 256, o_b = o_w + (w_b + 255) / 256 * 256;
     char* buf = nullptr;
@@ -944,7 +974,7 @@ ctf_status ctf_internal_decoder_texture(ctf_texture t)
     }
     t->dec_buf = buf;
     DevDecoderWeights& W = t->dec;
-    W.grid = latent_grid(d->desc, reinterpret_cast<const uint16_t*>(buf));
+    W.grid = infer_grid(d->desc, reinterpret_cast<const uint16_t*>(buf));
     W.precision = prec;
     W.w = reinterpret_cast<const uint16_t*>(buf + o_w);
     W.bias = reinterpret_cast<const float*>(buf + o_b);

@@ -272,14 +272,133 @@ __device__ __forceinline__ f4 latent_combine(const LatentFetch& F)
     return r;
 }
 
-// Forward pass of 16 texels whose features this lane holds (X = features
-// 4g..4g+3 of texel l%16).  Returns the output block (rows = channels; lanes
-// 0..15 hold RGBA of their texel) and, if wanted, the pre-activations.
+// Inference copy of the latents.  Each level is stored as (L+1) x (L+1)
+// cells, cell (i, j) holding cell (i mod L, j mod L), so that the four
+// corners of a sample are c, c + 1, c + (L+1), c + (L+2) with no wrapping.
+// For texel x, the sample point (x + 1/2) L / W - 1/2 equals
+// (2x + 1 - 2^s) / 2^(s+1) with W = 2^s L: the integer 2x + 1 - 2^s (taken
+// modulo 2^32, which keeps its low bits) holds the cell index mod L in bits
+// [s+1, s+1+log2 L) and the fraction in its low s+1 bits, for any x.
+struct InferGrid {
+    const uint16_t* __restrict__ base;
+    uint32_t lvl1;          // byte offset of level 1
+    int log_l0, log_l1;     // log2 of the sides
+    int shift0, shift1;     // log2(tex_w / side)
+    int tex_w;
+};
+
+// Per-lane constants of the inference fetch (level g/2, channels 4 (g%2)..+3).
 template <int P>
-__device__ __forceinline__ f4 mlp_forward(const FwdWeights<P>& W, const Biases& B, f4 X, f4* z1,
-                                          f4* z2)
+struct InferLane {
+    uint32_t off;      // byte offset of the level plus 8 (g % 2)
+    uint32_t pitch;    // L + 1 cells
+    uint32_t c;        // 1 - 2^s
+    uint32_t sh;       // s + 1
+    uint32_t logl;     // log2 L
+    float scale;       // 2^-(s+1)
+
+    __device__ __forceinline__ InferLane(const InferGrid& G, int g)
+    {
+        const bool l1 = g >= 2;
+        const int s = l1 ? G.shift1 : G.shift0;
+        logl = (uint32_t)(l1 ? G.log_l1 : G.log_l0);
+        pitch = (1u << logl) + 1u;
+        off = (l1 ? G.lvl1 : 0u) + 8u * (uint32_t)(g & 1);
+        c = 1u - (1u << s);
+        sh = (uint32_t)s + 1u;
+        scale = __builtin_bit_cast(float, (uint32_t)(127 - s - 1) << 23);
+    }
+};
+
+// The four corner vectors and the bilinear weights of one sample; fp16:
+// weights packed as (w0, w1), (w2, w3) -- each a multiple of 2^-2(s+1) below
+// 1, so exact in fp16 for s <= 4 (rounded to fp16 beyond); bf16: float.
+struct InferFetch {
+    u16x4 v[4];
+    uint32_t w01, w23;
+    float w[4];
+};
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+template <int P>
+__device__ __forceinline__ void infer_fetch(const InferGrid& G, const InferLane<P>& K, int x, int y, InferFetch& F)
 {
-    const u16x4 xb = pack4<P>(X);
+    const uint32_t gx = 2u * (uint32_t)x + K.c, gy = 2u * (uint32_t)y + K.c;
+    const uint32_t cx = __builtin_amdgcn_ubfe(gx, K.sh, K.logl);
+    const uint32_t cy = __builtin_amdgcn_ubfe(gy, K.sh, K.logl);
+    const float fx = (float)__builtin_amdgcn_ubfe(gx, 0u, K.sh) * K.scale;
+    const float fy = (float)__builtin_amdgcn_ubfe(gy, 0u, K.sh) * K.scale;
+    const uint32_t o0 = (__umul24(cy, K.pitch) + cx) * 16u + K.off;
+    const uint32_t o1 = o0 + K.pitch * 16u;
+    const char* __restrict__ b = reinterpret_cast<const char*>(G.base);
+    F.v[0] = *reinterpret_cast<const u16x4*>(b + o0);
+    F.v[1] = *reinterpret_cast<const u16x4*>(b + o0 + 16u);
+    F.v[2] = *reinterpret_cast<const u16x4*>(b + o1);
+    F.v[3] = *reinterpret_cast<const u16x4*>(b + o1 + 16u);
+    if (P == CTF_FP16) {
+        const h2 f = __builtin_bit_cast(h2, cvt2<CTF_FP16>(fx, fy));
+        const h2 one = {(_Float16)1.0f, (_Float16)1.0f};
+        const h2 i = one - f;                                       // (1 - fx, 1 - fy)
+        const h2 r = __builtin_shufflevector(i, f, 0, 2);           // (1 - fx, fx)
+        F.w01 = __builtin_bit_cast(uint32_t, r * __builtin_shufflevector(i, i, 1, 1));
+        F.w23 = __builtin_bit_cast(uint32_t, r * __builtin_shufflevector(f, f, 1, 1));
+    } else {
+        const float ifx = 1.0f - fx, ify = 1.0f - fy;
+        F.w[0] = ifx * ify;
+        F.w[1] = fx * ify;
+        F.w[2] = ifx * fy;
+        F.w[3] = fx * fy;
+    }
+}
+
+// The interpolated features of the sample as the layer-1 B operand.  fp16:
+// packed fp16 products and sums (v_pk_mul / v_pk_fma, each rounding to
+// fp16); bf16: float32 sums rounded once.
+template <int P>
+__device__ __forceinline__ u16x4 infer_combine(const InferFetch& F)
+{
+    if (P == CTF_FP16) {
+        const h2 w01 = __builtin_bit_cast(h2, F.w01), w23 = __builtin_bit_cast(h2, F.w23);
+        const h2 ws[4] = {__builtin_shufflevector(w01, w01, 0, 0), __builtin_shufflevector(w01, w01, 1, 1),
+                          __builtin_shufflevector(w23, w23, 0, 0), __builtin_shufflevector(w23, w23, 1, 1)};
+        // (a subscript applied directly to a __builtin_bit_cast result is
+        // miscompiled by this clang -- it reads element 0 -- so every
+        // reinterpreted vector is named before it is indexed)
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        u32x2 d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = __builtin_bit_cast(u32x2, F.v[q]);
+        u32x2 r;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const uint32_t d0 = d[0][half];
+            h2 acc = __builtin_bit_cast(h2, d0) * ws[0];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                const uint32_t dq = d[q][half];
+                acc = __builtin_elementwise_fma(__builtin_bit_cast(h2, dq), ws[q], acc);
+            }
+            r[half] = __builtin_bit_cast(uint32_t, acc);
+        }
+        return __builtin_bit_cast(u16x4, r);
+    } else {
+        f4 x = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[i] = __builtin_fmaf(F.w[q], Mfma<P>::load(F.v[q][i]), x[i]);
+        return pack4<P>(x);
+    }
+}
+
+// Forward pass of 16 texels whose features this lane holds (xb = features
+// 4g..4g+3 of texel l%16 in the operand format; mlp_forward takes them as
+// float).  Returns the output block (rows = channels; lanes 0..15 hold RGBA
+// of their texel) and, if wanted, the pre-activations.
+template <int P>
+__device__ __forceinline__ f4 mlp_forward_b(const FwdWeights<P>& W, const Biases& B, u16x4 xb, f4* z1, f4* z2)
+{
     f4 d1[4];
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb) d1[hb] = Mfma<P>::k16(W.w1[hb], xb, B.b1[hb]);
@@ -306,6 +425,12 @@ __device__ __forceinline__ f4 mlp_forward(const FwdWeights<P>& W, const Biases& 
         for (int i = 0; i < 4; ++i) z2[i] = d2[i];
     }
     return y;
+}
+
+template <int P>
+__device__ __forceinline__ f4 mlp_forward(const FwdWeights<P>& W, const Biases& B, f4 X, f4* z1, f4* z2)
+{
+    return mlp_forward_b<P>(W, B, pack4<P>(X), z1, z2);
 }
 
 }  // namespace ctf

@@ -113,52 +113,45 @@ __device__ __forceinline__ int dec_list_find(const uint64_t* keys, int n, uint64
     return lo;
 }
 
+// Rows past R read whatever the row list holds there (the index is kept
+// inside the list): the inference fetch maps any texel to cells inside the
+// grid, and those rows' results are never stored.
 template <int P>
-__device__ __forceinline__ void fetch_row(const int2* rows, int R, int row, const LatentGrid& G, int g,
-                                          LatentFetch& F)
+__device__ __forceinline__ void fetch_row(const int2* rows, int row, const InferGrid& G, const InferLane<P>& K,
+                                          InferFetch& F)
 {
-    const int2 p = row < R ? rows[row] : make_int2(0, 0);
-    latent_fetch(G, p.x, p.y, g, F);
+    const int2 p = rows[row & (kMaxItems - 1)];
+    infer_fetch<P>(G, K, p.x, p.y, F);
 }
 
 template <int P>
 __device__ __forceinline__ void finish_row(float4* vals, int R, int row, const FwdWeights<P>& W,
-                                           const Biases& Bz, const LatentFetch& F, int g)
+                                           const Biases& Bz, const InferFetch& F, int g)
 {
-    const f4 y = mlp_forward<P>(W, Bz, latent_combine<P>(F), nullptr, nullptr);
+    const f4 y = mlp_forward_b<P>(W, Bz, infer_combine<P>(F), nullptr, nullptr);
     if (g == 0 && row < R) vals[row] = make_float4(y[0], y[1], y[2], y[3]);
 }
 
 // rows[0..R) -> vals[0..R) in 16-row tiles, two fetch buffers in ping-pong.
-// Every prefetch is issued unconditionally (rows past R fetch cell 0), so
-// each path reaches the next tile's MLP with the same loads outstanding and
-// the wait before it covers only the current tile's gathers.
-// The same with the first tile's gathers already issued into fa.
+// Every prefetch is issued unconditionally, so each path reaches the next
+// tile's MLP with the same loads outstanding and the wait before it covers
+// only the current tile's gathers.
 template <int P>
-__device__ __forceinline__ void decode_rows_from(const int2* rows, float4* vals, int R, LatentFetch& fa,
-                                                 const LatentGrid& G, const FwdWeights<P>& W, const Biases& Bz,
-                                                 int j, int g)
+__device__ __forceinline__ void decode_rows(DecLds& L, int R, const InferGrid& G, const FwdWeights<P>& W,
+                                            const Biases& Bz, int j, int g)
 {
     const int T = (R + 15) >> 4;
     if (T == 0) return;
-    LatentFetch fb;
+    const InferLane<P> K(G, g);
+    InferFetch fa, fb;
+    fetch_row<P>(L.rows, j, G, K, fa);
     for (int t = 0; t < T; t += 2) {
-        fetch_row<P>(rows, R, 16 * (t + 1) + j, G, g, fb);
-        finish_row<P>(vals, R, 16 * t + j, W, Bz, fa, g);
+        fetch_row<P>(L.rows, 16 * (t + 1) + j, G, K, fb);
+        finish_row<P>(L.vals, R, 16 * t + j, W, Bz, fa, g);
         if (t + 1 >= T) break;
-        fetch_row<P>(rows, R, 16 * (t + 2) + j, G, g, fa);
-        finish_row<P>(vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
+        fetch_row<P>(L.rows, 16 * (t + 2) + j, G, K, fa);
+        finish_row<P>(L.vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
     }
-}
-
-template <int P>
-__device__ __forceinline__ void decode_rows(DecLds& L, int R, const LatentGrid& G, const FwdWeights<P>& W,
-                                            const Biases& Bz, int j, int g)
-{
-    if (R <= 0) return;
-    LatentFetch fa;
-    fetch_row<P>(L.rows, R, j, G, g, fa);
-    decode_rows_from<P>(L.rows, L.vals, R, fa, G, W, Bz, j, g);
 }
 
 __device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t tile, uint64_t act, uint64_t A,
@@ -189,7 +182,7 @@ __device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t ti
 // layer's coordinates); a.out / a.tile_stats / a.stf_xy point at this
 // layer's planes.
 template <int METHOD, int P, bool STATS, bool FB, int FILTER>
-__device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& G, const FwdWeights<P>& W,
+__device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G, const FwdWeights<P>& W,
                                          const Biases& Bz, DecLds& L, int64_t tile, int tx, int ty,
                                          const Footprint& f, FrameCounters& fc)
 {
@@ -459,19 +452,52 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const LatentGrid& 
     wave_lds_sync();  // the next tile reuses this wave's LDS slice
 }
 
+// Pixel offset of this lane inside its tile, (lane / 8) sw + lane % 8: a
+// tile's pixel addresses are a scalar base plus this per-lane constant.
+__device__ __forceinline__ uint32_t lane_pixel(const FilterArgs& a)
+{
+    const int lane = lane_id();
+    uint32_t lp = (uint32_t)(lane >> 3) * (uint32_t)a.sw + (uint32_t)(lane & 7);
+    // opaque to the optimizer, so that an access stays "scalar base + this
+    // 32-bit offset" (an SGPR-based global access) rather than a hoisted
+    // 64-bit per-lane pointer
+    asm volatile("" : "+v"(lp));
+    return lp;
+}
+
+// First pixel of tile (tx, ty) and whether all of its pixels are on screen
+// (both wave-uniform).
+__device__ __forceinline__ int64_t tile_pixel0(const FilterArgs& a, int tx, int ty)
+{
+    return (int64_t)ty * kTile * a.sw + (int64_t)tx * kTile;
+}
+
+__device__ __forceinline__ bool tile_interior(const FilterArgs& a, int tx, int ty)
+{
+    return tx * kTile + kTile <= a.sw && ty * kTile + kTile <= a.sh;
+}
+
+__device__ __forceinline__ bool lane_on_screen(const FilterArgs& a, int tx, int ty)
+{
+    if (tile_interior(a, tx, ty)) return true;
+    const int lane = lane_id();
+    return tx * kTile + (lane & 7) < a.sw && ty * kTile + (lane >> 3) < a.sh;
+}
+
 // Inputs of a tile for this lane, NaN (inactive) outside the band or screen.
 __device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
                                              float4& d)
 {
-    const int lane = lane_id();
     uv = make_float2(__builtin_nanf(""), 0.f);
     d = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t.tile >= band_e) return;
-    const int px = t.tx * kTile + (lane & 7), py = t.ty * kTile + (lane >> 3);
-    if (px < a.sw && py < a.sh) {
-        const int64_t q = (int64_t)py * a.sw + px;
-        uv = reinterpret_cast<const float2*>(a.uv)[q];
-        d = reinterpret_cast<const float4*>(a.duv)[q];
+    if (lane_on_screen(a, t.tx, t.ty)) {
+        const int64_t p0 = tile_pixel0(a, t.tx, t.ty);
+        const uint32_t lp = lane_pixel(a);
+        const char* const ub = reinterpret_cast<const char*>(reinterpret_cast<const float2*>(a.uv) + p0);
+        const char* const db = reinterpret_cast<const char*>(reinterpret_cast<const float4*>(a.duv) + p0);
+        uv = *reinterpret_cast<const float2*>(ub + lp * 8u);
+        d = *reinterpret_cast<const float4*>(db + lp * 16u);
     }
 }
 
@@ -566,17 +592,18 @@ struct Pending {
 // Plan one tile: decisions, staging rows (L.keys as int2), the rank table
 // and per-lane state of `slot`, debug outputs, tile record and counters.
 // Returns the tile's row count.
+// The rows go behind the batch's rows (from row `base`) when they fit there,
+// else to the staging area (L.keys) for the caller to move after a flush.
 template <int METHOD, bool STATS>
-__device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int slot, int64_t tile, int tx, int ty,
-                                         const Footprint& f, FrameCounters& fc)
+__device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int slot, int base, int64_t tile, int tx,
+                                         int ty, const Footprint& f, FrameCounters& fc)
 {
     DecLds& L = BL.L;
     int2* const stage = reinterpret_cast<int2*>(L.keys);
     uint8_t* const rank = slot ? BL.rank1 : L.rank;
     const int lane = lane_id();
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-    const bool in_screen = px < a.sw && py < a.sh;
-    const int64_t pix = (int64_t)py * a.sw + px;
+    const bool in_screen = lane_on_screen(a, tx, ty);
     const bool inA = f.active && f.magnify;
     const uint64_t act = ballot(f.active);
     const uint64_t A = ballot(inA);
@@ -584,13 +611,31 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
 
     int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
     constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
-    if ((kCollab || STATS) && nA > 0) {
+    // Mask and List only need a 16x16 window that holds every footprint of
+    // A: try the one centred on a lane of A (lane 36 when it is in A) before
+    // reducing the exact box.  Bit positions are relative to the window's
+    // corner; the texels, their order and every decision are the same.
+    bool window = false;
+    if constexpr ((METHOD == CTF_LIST || METHOD == CTF_MASK) && !STATS) {
+        if (nA > 0) {
+            const int rl = ((A >> 36) & 1ull) ? 36 : (int)__builtin_ctzll(A);
+            const int ox = __builtin_amdgcn_readlane(f.x0, rl) - 7, oy = __builtin_amdgcn_readlane(f.y0, rl) - 7;
+            const bool outside =
+                inA && ((uint32_t)f.x0 - (uint32_t)ox > 14u || (uint32_t)f.y0 - (uint32_t)oy > 14u);
+            if (ballot(outside) == 0) {
+                window = true;
+                xmin = ox;
+                ymin = oy;
+            }
+        }
+    }
+    if ((kCollab || STATS) && nA > 0 && !window) {
         xmin = wave_min(inA ? f.x0 : INT32_MAX);
         ymin = wave_min(inA ? f.y0 : INT32_MAX);
         bbw = wave_max(inA ? f.x0 + 1 : INT32_MIN) - xmin + 1;
         bbh = wave_max(inA ? f.y0 + 1 : INT32_MIN) - ymin + 1;
     }
-    const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+    const bool fits16 = window || (nA > 0 && bbw <= 16 && bbh <= 16);
 
     uint64_t B[4] = {0, 0, 0, 0};
     int nmask = 0;
@@ -658,27 +703,32 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
         pick = stf_pick_h(f, h1, h2);
     }
 
-    // staging rows (in the keys array) and the inverse table of Mask/List
+    // rows (behind the batch or in the staging area) and the inverse table
+    // of Mask/List.  Only the first tap of each footprint row is looked up
+    // at gather time: in a row-major list the texel right of a footprint
+    // texel is the next item.
     const int rank_act = mbcnt(act);
     const int ns = success ? n : 0;
     int R;
     if constexpr (METHOD == CTF_BILINEAR4) {
         R = 4 * popc64(act);
+        int2* const dst = base + R <= kMaxItems ? L.rows + base : stage;
         if (f.active) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) stage[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
+            for (int q = 0; q < 4; ++q) dst[4 * rank_act + q] = make_int2(f.x0 + (q & 1), f.y0 + (q >> 1));
         }
     } else {
         R = ns + nstf;
+        int2* const dst = base + R <= kMaxItems ? L.rows + base : stage;
         if (success) {
             if (sorted) {
-                // the lane's item indices first (they read the sorted keys),
-                // then the keys become staging rows in place
+                // the lane's item indices first (they read the sorted keys);
+                // in place when the rows go to the staging area
                 if (inA) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < 4; q += 2) {
                         const uint64_t key = ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                             (uint32_t)(f.x0 + (q & 1) - xmin);
+                                             (uint32_t)(f.x0 - xmin);
                         rank[4 * lane + q] = (uint8_t)dec_list_find(L.keys, n, key);
                     }
                 }
@@ -695,29 +745,32 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
                         ex = xmin + (int)(uint32_t)key;
                         ey = ymin + (int)(key >> 32);
                     }
-                    stage[i] = make_int2(ex, ey);
+                    dst[i] = make_int2(ex, ey);
                     if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
                 }
             } else {
-                int base = 0;
+                // bit `lane` of word w is position 64 w + lane of the window:
+                // column lane % 16, row 4 w + lane / 16
+                const int cx = xmin + (lane & 15);
+                int cy = ymin + (lane >> 4), first = 0;
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     if ((B[w] >> lane) & 1u) {
-                        const int r = base + mbcnt(B[w]);
-                        const int t = 64 * w + lane;
-                        const int2 c = make_int2(xmin + (t & 15), ymin + (t >> 4));
-                        rank[t] = (uint8_t)r;
-                        stage[r] = c;
-                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
+                        const int r = first + mbcnt(B[w]);
+                        rank[64 * w + lane] = (uint8_t)r;
+                        dst[r] = make_int2(cx, cy);
+                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = make_int2(cx, cy);
                     }
-                    base += popc64(B[w]);
+                    first += popc64(B[w]);
+                    cy += 4;
                 }
             }
         }
-        if (draws) stage[ns + mbcnt(stfmask)] = pick;
+        if (draws) dst[ns + mbcnt(stfmask)] = pick;
     }
     if (in_screen && a.stf_xy)
-        reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+        reinterpret_cast<int2*>(a.stf_xy)[tile_pixel0(a, tx, ty) + lane_pixel(a)] =
+            draws ? pick : make_int2(INT32_MIN, INT32_MIN);
     int gi = 0, gd = 0;
     if constexpr (METHOD == CTF_BILINEAR4) {
         gi = 4 * rank_act;
@@ -756,16 +809,17 @@ __device__ __forceinline__ void gather_tile(const FilterArgs& a, BatchLds& BL, i
     float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
     if (draws) res = vals[ls.misc & 0xff];
     if (exact) {
-        int idx[4] = {gi, gi + 1, gi + gd, gi + gd + 1};
+        // each footprint row is two consecutive items
+        int i0 = gi, i2 = gi + gd;
         if constexpr (METHOD == CTF_LIST || METHOD == CTF_MASK) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) idx[q] = rank[idx[q]];
+            i0 = rank[i0];
+            i2 = rank[i2];
         }
-        res = bilerp(ls.s, ls.t, vals[idx[0]], vals[idx[1]], vals[idx[2]], vals[idx[3]]);
+        res = bilerp(ls.s, ls.t, vals[i0], vals[i0 + 1], vals[i2], vals[i2 + 1]);
     }
     if (in_screen) {
-        const int px = pd.tx * kTile + (lane & 7), py = pd.ty * kTile + (lane >> 3);
-        reinterpret_cast<float4*>(a.out)[(int64_t)py * a.sw + px] = res;
+        char* const ob = reinterpret_cast<char*>(reinterpret_cast<float4*>(a.out) + tile_pixel0(a, pd.tx, pd.ty));
+        *reinterpret_cast<float4*>(ob + lane_pixel(a) * 16u) = res;
     }
 }
 
@@ -778,7 +832,7 @@ struct Batch {
 
 // Decode the batch and gather its tiles in slot order.
 template <int METHOD, int P>
-__device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, Batch& bt, const LatentGrid& G,
+__device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, Batch& bt, const InferGrid& G,
                                             const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc)
 {
     const int lane = lane_id();
@@ -796,23 +850,23 @@ __device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, B
 // Plan a tile and append its rows to the batch (decoding the batch first
 // when it is full or the rows do not fit behind it).
 template <int METHOD, int P, bool STATS>
-__device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Batch& bt, const LatentGrid& G,
+__device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Batch& bt, const InferGrid& G,
                                           const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc,
                                           const TileWalk& cur, const Footprint& f)
 {
     const int lane = lane_id();
     if (bt.npend == 2) batch_flush<METHOD, P>(a, BL, bt, G, W, Bz, fc);
-    const int R = plan_tile<METHOD, STATS>(a, BL, bt.npend, cur.tile, cur.tx, cur.ty, f, fc);
+    const int R = plan_tile<METHOD, STATS>(a, BL, bt.npend, bt.rows, cur.tile, cur.tx, cur.ty, f, fc);
     if (bt.rows + R > kMaxItems) {
-        // planned into slot 1: decode slot 0, then move the state and table
+        // planned into slot 1 with its rows staged: decode slot 0, then move
+        // the state, the table and the rows
         batch_flush<METHOD, P>(a, BL, bt, G, W, Bz, fc);
         BL.st[0][lane] = BL.st[1][lane];
         reinterpret_cast<uint32_t*>(BL.L.rank)[lane] = reinterpret_cast<const uint32_t*>(BL.rank1)[lane];
+        const int2* stage = reinterpret_cast<const int2*>(BL.L.keys);
+        for (int i = lane; i < R; i += kWave) BL.L.rows[i] = stage[i];
     }
-    wave_lds_sync();
-    const int2* stage = reinterpret_cast<const int2*>(BL.L.keys);
-    for (int i = lane; i < R; i += kWave) BL.L.rows[bt.rows + i] = stage[i];
-    wave_lds_sync();   // the next plan rewrites the staging rows
+    wave_lds_sync();   // the next plan rewrites the keys
     Pending& pd = bt.npend ? bt.p1 : bt.p0;
     pd.tile = cur.tile;
     pd.tx = cur.tx;

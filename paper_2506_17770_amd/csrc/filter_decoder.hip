@@ -85,14 +85,15 @@ __global__ __launch_bounds__(256, 2) void k_decoder_eval(DevDecoderWeights D, co
     Bz.load(D.bias, lane);
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const InferLane<P> K(D.grid, g);
     const int64_t ntiles = (n + 15) / 16;
     for (int64_t t = gw; t < ntiles; t += nw) {
         const int64_t row = t * 16 + j;
         const bool valid = row < n;
         const int2 p = valid ? xy[row] : make_int2(0, 0);
-        LatentFetch F;
-        latent_fetch(D.grid, p.x, p.y, g, F);
-        const f4 y = mlp_forward<P>(W, Bz, latent_combine<P>(F), nullptr, nullptr);
+        InferFetch F;
+        infer_fetch<P>(D.grid, K, p.x, p.y, F);
+        const f4 y = mlp_forward_b<P>(W, Bz, infer_combine<P>(F), nullptr, nullptr);
         if (g == 0 && valid) out[row] = make_float4(y[0], y[1], y[2], y[3]);
     }
 }
