@@ -484,9 +484,28 @@ __device__ __forceinline__ bool lane_on_screen(const FilterArgs& a, int tx, int 
     return tx * kTile + (lane & 7) < a.sw && ty * kTile + (lane >> 3) < a.sh;
 }
 
-// Inputs of a tile for this lane, NaN (inactive) outside the band or screen.
+// Inputs of a tile for this lane, NaN (inactive) outside the band or screen
+// (per-lane 64-bit addresses: the per-tile kernels run faster with these
+// than with load_tile_px_s, measured).
 __device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
                                              float4& d)
+{
+    const int lane = lane_id();
+    uv = make_float2(__builtin_nanf(""), 0.f);
+    d = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t.tile >= band_e) return;
+    const int px = t.tx * kTile + (lane & 7), py = t.ty * kTile + (lane >> 3);
+    if (px < a.sw && py < a.sh) {
+        const int64_t q = (int64_t)py * a.sw + px;
+        uv = reinterpret_cast<const float2*>(a.uv)[q];
+        d = reinterpret_cast<const float4*>(a.duv)[q];
+    }
+}
+
+// The same with a scalar tile base plus the lane's offset (the batched
+// kernel).
+__device__ __forceinline__ void load_tile_px_s(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
+                                               float4& d)
 {
     uv = make_float2(__builtin_nanf(""), 0.f);
     d = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -894,13 +913,13 @@ __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterAr
     float2 uv_next;
     float4 d_next;
     TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
-    load_tile_px(a, next, band.end, uv_next, d_next);
+    load_tile_px_s(a, next, band.end, uv_next, d_next);
     while (next.tile < band.end) {
         const TileWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
         next.advance(band.nw);
-        load_tile_px(a, next, band.end, uv_next, d_next);
+        load_tile_px_s(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
         batch_add<METHOD, P, STATS>(a, BL, bt, D.grid, W, Bz, fc, cur, f);
     }
