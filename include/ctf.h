@@ -261,7 +261,7 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float *uv, const float *uv_d
  * ------------------------------------------------------------------------- */
 
 typedef struct ctf_decoder_desc {
-    int32_t l0, l1;      /* latent grid sides; tex_w / l0 and tex_w / l1 powers of two */
+    int32_t l0, l1;      /* latent grid sides, 2..8192; tex_w / l0 and tex_w / l1 powers of two */
     int32_t hidden;      /* MLP width H (multiple of 4, <= 64): 2C -> H -> H -> 4, ReLU */
     int32_t channels;    /* latent channels per level C: 8 */
     int32_t tex_w;       /* side of the square texel lattice the latents cover */

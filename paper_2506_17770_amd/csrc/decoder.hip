@@ -780,6 +780,8 @@ ctf_status ctf_decoder_create(ctf_context ctx, const ctf_decoder_desc* desc, con
     if (!pow2(d.tex_w) || !pow2(d.l0) || !pow2(d.l1) || d.l0 > d.tex_w || d.l1 > d.tex_w || d.l0 < 2 || d.l1 < 2 ||
         d.tex_w > (1 << 22))
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_create: tex_w, l0, l1 powers of two, 2 <= l <= tex_w");
+    // latent byte offsets are 32-bit (the inference copy pads each level to (l+1)^2 cells)
+    if (d.l0 > 8192 || d.l1 > 8192) return fail(CTF_ERR_UNSUPPORTED, "ctf_decoder_create: l0, l1 above 8192");
     DeviceScope ds(ctx->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_create: set device");
     ctf_decoder dec = new (std::nothrow) ctf_decoder_s;

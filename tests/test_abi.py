@@ -45,3 +45,23 @@ def test_no_device_gives_a_clean_error_or_a_context():
     rc = ctf.lib.ctf_create(0, ctypes.byref(h))
     assert rc != 0
     assert ctf.lib.ctf_last_error()
+
+
+def test_decoder_create_validates_sizes_before_the_device():
+    """Argument checks of ctf_decoder_create return before any device work
+    (a dummy context handle is never dereferenced on these paths)."""
+    import numpy as np
+    import paper_2506_17770_amd as ctf
+    dummy_ctx = ctypes.c_void_p(1)
+    init = np.zeros(4, np.float32)
+    h = ctypes.c_void_p()
+    cases = [((16384, 4, 64, 8, 16384), 2),   # latent sides above 8192 (32-bit offsets)
+             ((512, 128, 64, 4, 2048), 2),    # channels must be 8
+             ((512, 128, 62, 8, 2048), 2),    # hidden must be a multiple of 4
+             ((500, 128, 64, 8, 2048), 1),    # sides must be powers of two
+             ((4096, 128, 64, 8, 2048), 1)]   # l0 above tex_w
+    for fields, want in cases:
+        d = ctf.DecoderDesc(*fields)
+        st = ctf.lib.ctf_decoder_create(dummy_ctx, ctypes.byref(d), init.ctypes.data, ctypes.byref(h))
+        assert st == want, (fields, st, ctf.lib.ctf_last_error())
+        assert ctf.lib.ctf_last_error()
