@@ -360,12 +360,25 @@ struct DevTexture {
 // 1/2 + 1/2 sum_k a_k sin(2 pi r_k / W), r_k = (p x + q y + j) mod W.  The
 // phase is an exact integer, r/W is exact in float32, and v_sin_f32 takes
 // its argument in revolutions, so each term is one hardware sine.
-__device__ __forceinline__ float sinusoid_channel(const int4* __restrict__ tc, int K,
-                                                  uint32_t wmask, float inv_w, int xm, int ym)
+// The term arrays in device memory are read through the constant address
+// space: with a wave-uniform address each term is one scalar load
+// (s_load_dwordx4 through the scalar cache) instead of a 64-lane broadcast
+// vector load and its wait.  Only for global memory that the kernel never
+// writes -- LDS-staged terms keep their generic pointer.
+typedef int TermVec __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) TermVec* ConstTerms;
+
+__device__ __forceinline__ ConstTerms const_terms(const int4* global_terms)
+{
+    return (ConstTerms)global_terms;
+}
+
+template <class TermPtr>
+__device__ __forceinline__ float sinusoid_channel(TermPtr tc, int K, uint32_t wmask, float inv_w, int xm, int ym)
 {
     float acc = 0.0f;
     for (int k = 0; k < K; ++k) {
-        const int4 tk = tc[k];
+        const auto tk = tc[k];
         const uint32_t r = (uint32_t)(__mul24(tk.x, xm) + __mul24(tk.y, ym) + tk.z) & wmask;
         const float sn = __builtin_amdgcn_sinf((float)r * inv_w);
         acc = __builtin_fmaf(__int_as_float(tk.w), sn, acc);
@@ -380,10 +393,11 @@ __device__ __forceinline__ float4 texel_eval(const DevTexture& T, int x, int y)
     if constexpr (KIND == CTF_TEX_SINUSOIDS) {
         const int xm = x & (int)T.wmask, ym = y & (int)T.wmask;
         const int K = T.n_terms;
-        r.x = sinusoid_channel(T.terms + 0 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.y = sinusoid_channel(T.terms + 1 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.z = sinusoid_channel(T.terms + 2 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.w = sinusoid_channel(T.terms + 3 * K, K, T.wmask, T.inv_w, xm, ym);
+        const ConstTerms tc = const_terms(T.terms);
+        r.x = sinusoid_channel(tc + 0 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.y = sinusoid_channel(tc + 1 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.z = sinusoid_channel(tc + 2 * K, K, T.wmask, T.inv_w, xm, ym);
+        r.w = sinusoid_channel(tc + 3 * K, K, T.wmask, T.inv_w, xm, ym);
     } else if constexpr (KIND == CTF_TEX_AFFINE) {
         const float fx = (float)x, fy = (float)y;
         r.x = __builtin_fmaf(T.affine[0][2], fy, __builtin_fmaf(T.affine[0][1], fx, T.affine[0][0]));
