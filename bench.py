@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MLP_FLOP = 2 * (16 * 64 + 64 * 64 + 64 * 4)      # useful FLOP per decoded texel
+PROC_SLOTS_PER_TERM = 11                      # 7 full-rate VALU + v_sin_f32 (quarter rate: 4 slots)
+VALU_SLOT_PEAK = 256 * 4 * 32 * 2.4e9          # full-rate VALU lane-ops/s: 157.3 TFLOP/s fp32 / 2
 PEAK_FP16_TFLOPS = 2500.0                          # MI355X dense fp16/bf16 MFMA
 
 
@@ -167,12 +169,24 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                      "not_exact_fraction": st["stf"] / max(1, st["active"]),
                      "waves_failed": st["tiles_fail"], "waves_ok": st["tiles_ok"]}
     b4 = res["bilinear4"]["gpixels_per_s"]
+    # ALU roofline of the texel evaluations: per term 7 full-rate VALU
+    # instructions (2 mul24, add3, and, cvt, mul, fma) and one v_sin_f32 at
+    # quarter rate = 11 lane slots; peak = 256 CUs x 4 SIMDs x 32 lanes x
+    # 2.4 GHz (the fp32 vector rate, one FMA per lane slot)
+    slots_per_eval = 4 * 32 * PROC_SLOTS_PER_TERM
     for v in res.values():
         v["speedup_vs_bilinear4"] = v["gpixels_per_s"] / b4
+        evals = v["texel_evals_per_pixel"] * npx
+        v["alu_frac"] = evals * slots_per_eval / (v["ms"] * 1e-3) / VALU_SLOT_PEAK
+    lst = res["list"]
+    achieved = lst["texel_evals_per_pixel"] * npx * slots_per_eval / (lst["ms"] * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12, "unit": "T lane-slots/s",
+            "frac": achieved / VALU_SLOT_PEAK, "kernel": "k_filter_simt<LIST, SINUSOIDS>",
+            "work_per_launch": f"{lst['texel_evals_per_pixel'] * npx:.0f} texel evals x {slots_per_eval} slots"}
     tex.close()
     return {"workload": "1920x1080 four-plane frame, 2048^2 procedural texture (K=32 sinusoids "
                         "per channel, F=64), per-lane texel production; *_8x4: the paper's 8x4 tiles, "
-                        "two per wave64", "methods": res}
+                        "two per wave64", "roofline": roof, "methods": res}
 
 
 def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
