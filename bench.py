@@ -365,6 +365,10 @@ def main():
         "mlp_rows_per_pixel": s_col["rows"] / npx,
         "decoder": {"psnr_db": psnr, "max_abs_err": max_abs, "psnr_db_untrained": psnr_init,
                     "train_seconds": train_s, "train_final_loss": float(tr[-1]) if args.train_steps else None,
+                    # MLP work of training: forward + backward (two GEMMs per layer) = 3x the forward
+                    "train_mlp_tflops": (args.train_steps * args.batch * 3 * MLP_FLOP / train_s / 1e12
+                                         if args.train_steps and train_s > 0 else None),
+                    "train_samples_per_s": args.train_steps * args.batch / train_s if train_s > 0 else None,
                     "reference": "GPU float32 procedural texels (within 3e-7 of float64)"},
         "wall_s": {"collaborative": wall_col, "bilinear4": wall_b4},
         "roofline": roof,
