@@ -2,9 +2,10 @@
 // 32 lanes (Section 3: 8x4 pixels per wave32), two per wave64, one per
 // half-wave.  Each half-wave takes its own collaborative step (Box, Mask,
 // List, remapping and the one-tap fallback) exactly as a wave32 would, so
-// the success regions of Figure 4 and the evaluation counts can be checked
-// on hardware.  Per-lane texel production, bilinear filter, one-tap STF
-// fallback.
+// the success regions of Figure 4 (bilinear) and of the bicubic maps of the
+// supplement's additional bicubic results, and the evaluation counts, can
+// be checked on hardware.  Per-lane texel production, bilinear or bicubic
+// (FxF footprints, F = 2 or 4) filters, one-tap STF fallback.
 //
 // Half-wave quantities are computed for both halves as scalars (ballots
 // split into their 32-bit halves, DPP reductions combined per pair of
@@ -19,9 +20,10 @@ namespace {
 constexpr int kW32Waves = 4;
 constexpr int kHalfItems = kMaxItems / 2;  // n <= k |A| <= 4 * 32 per half
 
+template <int F>
 struct W32Lds {
     float4 vals[2][kHalfItems];   // produced texel values, by half and item
-    uint64_t keys[kMaxItems];     // List past 16x16: sorted unique keys, half in bit 62
+    uint64_t keys[kWave * F * F]; // List past 16x16: sorted unique keys, half in bit 62
     uint16_t items[2][256];       // Mask: item i -> position t = h(i, B)
     uint8_t rank[2][256];         // Mask: position t -> item index h^-1(t, B)
     uint8_t bytes[2][256];        // footprint-corner scatter before the ballots
@@ -43,24 +45,27 @@ __device__ __forceinline__ void halves_reduce(int v, Op op, int& r0, int& r1)
 __device__ __forceinline__ uint32_t lo32(uint64_t m) { return (uint32_t)m; }
 __device__ __forceinline__ uint32_t hi32(uint64_t m) { return (uint32_t)(m >> 32); }
 
-// Sorted unique keys of both halves (half 0 first); returns the total and
-// the number of half-0 keys in n0.
-__device__ int w32_list_sorted(W32Lds& L, bool inA, int h, const Footprint& f, int xmin, int ymin, int& n0)
+// Sorted unique keys of both halves (half 0 first) over the FxF footprints
+// with upper-left taps (ox, oy); returns the total and the number of half-0
+// keys in n0.
+template <int F>
+__device__ int w32_list_sorted(W32Lds<F>& L, bool inA, int h, int ox, int oy, int xmin, int ymin, int& n0)
 {
+    constexpr int N = kWave * F * F;
     const int lane = lane_id();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < F * F; ++q) {
         uint64_t key = ~0ull;
         if (inA)
-            key = ((uint64_t)h << 62) | ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                  (uint32_t)(f.x0 + (q & 1) - xmin);
-        L.keys[4 * lane + q] = key;
+            key = ((uint64_t)h << 62) | ((uint64_t)(uint32_t)(oy + q / F - ymin) << 32) |
+                  (uint32_t)(ox + q % F - xmin);
+        L.keys[F * F * lane + q] = key;
     }
-    for (int size = 2; size <= kMaxItems; size <<= 1)
+    for (int size = 2; size <= N; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             wave_lds_sync();
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
+            for (int hh = 0; hh < N / (2 * kWave); ++hh) {
                 const int p = lane + kWave * hh;
                 const int i = (p / stride) * stride * 2 + (p % stride);
                 const int j = i + stride;
@@ -74,7 +79,7 @@ __device__ int w32_list_sorted(W32Lds& L, bool inA, int h, const Footprint& f, i
         }
     int base = 0;
     n0 = 0;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < N / kWave; ++c) {
         wave_lds_sync();
         const int i = kWave * c + lane;
         const uint64_t k = L.keys[i];
@@ -89,7 +94,8 @@ __device__ int w32_list_sorted(W32Lds& L, bool inA, int h, const Footprint& f, i
     return base;
 }
 
-__device__ __forceinline__ int w32_find(const W32Lds& L, int lo, int hi, uint64_t key)
+template <int F>
+__device__ __forceinline__ int w32_find(const W32Lds<F>& L, int lo, int hi, uint64_t key)
 {
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -104,14 +110,15 @@ struct HalfDecision {
     bool cap_ok, count_ok, success;
 };
 
-template <int METHOD, int TEX, bool STATS>
+template <int METHOD, int TEX, bool STATS, int FILTER>
 __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, DevTexture T)
 {
-    __shared__ W32Lds lds_all[kW32Waves];
+    constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
+    __shared__ W32Lds<F> lds_all[kW32Waves];
     const int wid = wave_in_block();
     const int lane = lane_id();
     const int h = lane >> 5, ll = lane & 31;
-    W32Lds& L = lds_all[wid];
+    W32Lds<F>& L = lds_all[wid];
     FrameCounters fc;
     const int64_t npairs = (a.ntiles + 1) / 2;
     const int64_t nw = (int64_t)gridDim.x * kW32Waves;
@@ -134,6 +141,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
             f = footprint(uv.x, uv.y, d, (float)T.width, (float)T.height);
         }
         const bool inA = f.active && f.magnify;
+        const int ox = f.x0 - O, oy = f.y0 - O;   // upper-left tap of the FxF footprint
         const uint64_t act = ballot(f.active);
         const uint64_t Aw = ballot(inA);
         const uint64_t Hm = h ? 0xffffffff00000000ull : 0x00000000ffffffffull;
@@ -146,10 +154,10 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         int xmin0 = 0, ymin0 = 0, xmax0 = -1, ymax0 = -1, xmin1 = 0, ymin1 = 0, xmax1 = -1, ymax1 = -1;
         constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
         if ((kCollab || STATS) && (nA0 | nA1)) {
-            halves_reduce(inA ? f.x0 : INT32_MAX, MinOp(), xmin0, xmin1);
-            halves_reduce(inA ? f.y0 : INT32_MAX, MinOp(), ymin0, ymin1);
-            halves_reduce(inA ? f.x0 + 1 : INT32_MIN, MaxOp(), xmax0, xmax1);
-            halves_reduce(inA ? f.y0 + 1 : INT32_MIN, MaxOp(), ymax0, ymax1);
+            halves_reduce(inA ? ox : INT32_MAX, MinOp(), xmin0, xmin1);
+            halves_reduce(inA ? oy : INT32_MAX, MinOp(), ymin0, ymin1);
+            halves_reduce(inA ? ox + F - 1 : INT32_MIN, MaxOp(), xmax0, xmax1);
+            halves_reduce(inA ? oy + F - 1 : INT32_MIN, MaxOp(), ymax0, ymax1);
         }
         const int bbw0 = nA0 ? xmax0 - xmin0 + 1 : 0, bbh0 = nA0 ? ymax0 - ymin0 + 1 : 0;
         const int bbw1 = nA1 ? xmax1 - xmin1 + 1 : 0, bbh1 = nA1 ? ymax1 - ymin1 + 1 : 0;
@@ -169,7 +177,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
             reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
             reinterpret_cast<uint32_t*>(L.bytes)[kWave + lane] = 0u;
             wave_lds_sync();
-            if (inA && fits16) L.bytes[h][16 * (f.y0 - ymin) + (f.x0 - xmin)] = 1;
+            if (inA && fits16) L.bytes[h][16 * (oy - ymin) + (ox - xmin)] = 1;
             wave_lds_sync();
             uint64_t C0[4], C1[4];
 #pragma unroll
@@ -179,8 +187,8 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                 C0[w] = (uint64_t)lo32(b0) | ((uint64_t)lo32(b1) << 32);
                 C1[w] = (uint64_t)hi32(b0) | ((uint64_t)hi32(b1) << 32);
             }
-            if (fits0) footprint_mask(C0, B0);
-            if (fits1) footprint_mask(C1, B1);
+            if (fits0) footprint_mask_f<F>(C0, B0);
+            if (fits1) footprint_mask_f<F>(C1, B1);
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const uint64_t* Bh = hh ? B1 : B0;
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         int n0s = 0, ntot = 0;
         if constexpr (METHOD == CTF_LIST) {
             if ((nA0 && !fits0) || (nA1 && !fits1)) {
-                ntot = w32_list_sorted(L, inA, h, f, xmin, ymin, n0s);
+                ntot = w32_list_sorted<F>(L, inA, h, ox, oy, xmin, ymin, n0s);
                 sorted = true;
             }
         }
@@ -243,7 +251,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         if constexpr (STATS && METHOD != CTF_LIST) {
             if ((nA0 && !fits0) || (nA1 && !fits1)) {
                 int n0u = 0;
-                const int nu = w32_list_sorted(L, inA, h, f, xmin, ymin, n0u);
+                const int nu = w32_list_sorted<F>(L, inA, h, ox, oy, xmin, ymin, n0u);
                 if (nA0 && !fits0) D[0].unique = n0u;
                 if (nA1 && !fits1) D[1].unique = nu - n0u;
             }
@@ -271,14 +279,30 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         // ---- production: each lane evaluates at most one texel per round
         float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
         int2 pick = make_int2(INT32_MIN, INT32_MIN);
-        if (draws) pick = stf_pick(f, a.seed, a.layer, px, py);
+        if (draws) {
+            uint32_t h1, h2;
+            stf_hashes(a.seed, a.layer, px, py, h1, h2);
+            pick = stf_pick_filter<FILTER>(f, h1, h2);
+        }
         if constexpr (METHOD == CTF_BILINEAR4) {
             if (exact) {
-                const float4 v0 = texel_eval<TEX>(T, f.x0, f.y0);
-                const float4 v1 = texel_eval<TEX>(T, f.x0 + 1, f.y0);
-                const float4 v2 = texel_eval<TEX>(T, f.x0, f.y0 + 1);
-                const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
-                res = bilerp(f.s, f.t, v0, v1, v2, v3);
+                if constexpr (F == 2) {
+                    const float4 v0 = texel_eval<TEX>(T, f.x0, f.y0);
+                    const float4 v1 = texel_eval<TEX>(T, f.x0 + 1, f.y0);
+                    const float4 v2 = texel_eval<TEX>(T, f.x0, f.y0 + 1);
+                    const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
+                    res = bilerp(f.s, f.t, v0, v1, v2, v3);
+                } else {
+                    float wx[4], wy[4];
+                    taps32<FILTER>(f.s, wx);
+                    taps32<FILTER>(f.t, wy);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float4 r = row4(wx, texel_eval<TEX>(T, ox, oy + j), texel_eval<TEX>(T, ox + 1, oy + j),
+                                              texel_eval<TEX>(T, ox + 2, oy + j), texel_eval<TEX>(T, ox + 3, oy + j));
+                        res = col_acc(wy[j], r, res, j == 0);
+                    }
+                }
             }
         } else {
             for (int round = 0; round < (kCollab ? k : 1); ++round) {
@@ -313,30 +337,34 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
             if constexpr (kCollab) {
                 wave_lds_sync();
                 if (exact) {
-                    int idx[4];
-                    if constexpr (METHOD == CTF_BOX) {
-                        const int b = (f.x0 - xmin) + (f.y0 - ymin) * bbw;
-                        idx[0] = b;
-                        idx[1] = b + 1;
-                        idx[2] = b + bbw;
-                        idx[3] = b + bbw + 1;
-                    } else if (half_sorted) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const uint64_t key = ((uint64_t)h << 62) |
-                                                 ((uint64_t)(uint32_t)(f.y0 + (q >> 1) - ymin) << 32) |
-                                                 (uint32_t)(f.x0 + (q & 1) - xmin);
-                            idx[q] = w32_find(L, key_off, key_off + n, key) - key_off;
+                    // item index of tap (i, j) of this half's list
+                    auto item_of = [&](int i, int j) -> int {
+                        if constexpr (METHOD == CTF_BOX) {
+                            return (ox + i - xmin) + (oy + j - ymin) * bbw;
+                        } else {
+                            if (half_sorted) {
+                                const uint64_t key = ((uint64_t)h << 62) |
+                                                     ((uint64_t)(uint32_t)(oy + j - ymin) << 32) |
+                                                     (uint32_t)(ox + i - xmin);
+                                return w32_find<F>(L, key_off, key_off + n, key) - key_off;
+                            }
+                            return L.rank[h][16 * (oy + j - ymin) + (ox + i - xmin)];
                         }
+                    };
+                    if constexpr (F == 2) {
+                        res = bilerp(f.s, f.t, L.vals[h][item_of(0, 0)], L.vals[h][item_of(1, 0)],
+                                     L.vals[h][item_of(0, 1)], L.vals[h][item_of(1, 1)]);
                     } else {
-                        const int t = 16 * (f.y0 - ymin) + (f.x0 - xmin);
-                        idx[0] = L.rank[h][t];
-                        idx[1] = L.rank[h][t + 1];
-                        idx[2] = L.rank[h][t + 16];
-                        idx[3] = L.rank[h][t + 17];
+                        float wx[4], wy[4];
+                        taps32<FILTER>(f.s, wx);
+                        taps32<FILTER>(f.t, wy);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float4 r = row4(wx, L.vals[h][item_of(0, j)], L.vals[h][item_of(1, j)],
+                                                  L.vals[h][item_of(2, j)], L.vals[h][item_of(3, j)]);
+                            res = col_acc(wy[j], r, res, j == 0);
+                        }
                     }
-                    res = bilerp(f.s, f.t, L.vals[h][idx[0]], L.vals[h][idx[1]], L.vals[h][idx[2]],
-                                 L.vals[h][idx[3]]);
                 }
             }
         }
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         const uint32_t Am[2] = {lo32(Aw), hi32(Aw)};
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
-            if constexpr (METHOD == CTF_BILINEAR4) evals[hh] = 4 * __popc(actm[hh]);
+            if constexpr (METHOD == CTF_BILINEAR4) evals[hh] = F * F * __popc(actm[hh]);
             else evals[hh] = (D[hh].success ? D[hh].n : 0) + __popc(stfm[hh]);
         }
         if (ll == 0 && tile_ok && a.tile_stats) {
@@ -385,7 +413,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
 
-template <int METHOD, int TEX>
+template <int METHOD, int TEX, int FILTER>
 hipError_t launch_w32_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
 {
     int dev = 0, cus = 256;
@@ -394,21 +422,34 @@ hipError_t launch_w32_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t 
     int64_t blocks = (npairs + kW32Waves - 1) / kW32Waves;
     if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
     if (a.tile_stats)
-        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0, s, a, T);
+        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0,
+                           s, a, T);
     else
-        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0, s, a, T);
+        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0,
+                           s, a, T);
     return hipGetLastError();
+}
+
+template <int TEX, int FILTER>
+hipError_t launch_w32_tf(const FilterArgs& a, const DevTexture& T, hipStream_t s)
+{
+    switch (a.method) {
+    case CTF_BILINEAR4: return launch_w32_m_t<CTF_BILINEAR4, TEX, FILTER>(a, T, s);
+    case CTF_STF1: return launch_w32_m_t<CTF_STF1, TEX, FILTER>(a, T, s);
+    case CTF_LIST: return launch_w32_m_t<CTF_LIST, TEX, FILTER>(a, T, s);
+    case CTF_BOX: return launch_w32_m_t<CTF_BOX, TEX, FILTER>(a, T, s);
+    case CTF_MASK: return launch_w32_m_t<CTF_MASK, TEX, FILTER>(a, T, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int TEX>
 hipError_t launch_w32_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
 {
-    switch (a.method) {
-    case CTF_BILINEAR4: return launch_w32_m_t<CTF_BILINEAR4, TEX>(a, T, s);
-    case CTF_STF1: return launch_w32_m_t<CTF_STF1, TEX>(a, T, s);
-    case CTF_LIST: return launch_w32_m_t<CTF_LIST, TEX>(a, T, s);
-    case CTF_BOX: return launch_w32_m_t<CTF_BOX, TEX>(a, T, s);
-    case CTF_MASK: return launch_w32_m_t<CTF_MASK, TEX>(a, T, s);
+    switch (a.filter) {
+    case CTF_FILTER_BILINEAR: return launch_w32_tf<TEX, CTF_FILTER_BILINEAR>(a, T, s);
+    case CTF_FILTER_BSPLINE: return launch_w32_tf<TEX, CTF_FILTER_BSPLINE>(a, T, s);
+    case CTF_FILTER_CATMULL_ROM: return launch_w32_tf<TEX, CTF_FILTER_CATMULL_ROM>(a, T, s);
     default: return hipErrorInvalidValue;
     }
 }

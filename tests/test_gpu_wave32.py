@@ -1,6 +1,7 @@
 """The paper's 8x4 wave shape on the GPU (two 8x4 tiles per wave64, one per
-half-wave) against the oracle run with 8x4 tiles, and the paper's Figure 4
-thresholds reproduced by the hardware kernel.
+half-wave) against the oracle run with 8x4 tiles, with the bilinear and the
+bicubic filters, and the paper's Figure 4 thresholds and bicubic lookup maps
+reproduced by the hardware kernel.
 
 Bar: tile records, lists, draws and counts exact; colours within 1e-6.
 """
@@ -111,7 +112,65 @@ def test_wave32_shape_rejects_unbuilt_combinations(G):
     tex = ctx.sinusoid_texture(64, pqj, amp)
     uv, duv = torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda()
     for m in (ctf.method(ctf.LIST, fallback=ctf.FB_C, wave_shape=ctf.WAVE_8X4),
-              ctf.method(ctf.LIST, filter=ctf.FILTER_BSPLINE, wave_shape=ctf.WAVE_8X4)):
+              ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS, filter=ctf.FILTER_BSPLINE, wave_shape=ctf.WAVE_8X4)):
         with pytest.raises(ctf.CtfError, match="8x4"):
             ctx.filter(uv, duv, tex, m)
+    tex.close()
+
+
+CUBIC_METHODS = [("full16", 0, O.BILINEAR4, (0, 0), 1), ("stf1", 1, O.STF1, (0, 0), 1),
+                 ("list", 2, O.LIST, (0, 0), 1), ("list_k2", 2, O.LIST, (0, 0), 2),
+                 ("box", 3, O.BOX, (0, 0), 2), ("mask_k2", 4, O.MASK, (0, 0), 2)]
+
+
+@pytest.mark.parametrize("filt", [1, 2], ids=["bspline", "catmull_rom"])
+@pytest.mark.parametrize("name,gk,ok,box,k", CUBIC_METHODS)
+def test_wave32_shape_bicubic_parity(G, filt, name, gk, ok, box, k):
+    """Bicubic filters (4x4 footprints) on 8x4 waves against the oracle with
+    8x4 tiles; with per-tile records and, for the collaborative methods,
+    without (the kernels the benchmark times)."""
+    from test_gpu_filter import compare
+    ctf, ctx, torch = G
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=8)
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    otex = O.sinusoid_texture(64, pqj, amp)
+    for sname, (uv, duv) in _scenes():
+        m = ctf.method(gk, box=box, k=k, filter=filt, wave_shape=ctf.WAVE_8X4)
+        g = run_w32(G, uv, duv, tex, m, seed=12)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box, k=k, filter=filt), seed=12, tile=(8, 4), lists=True,
+                     stf=True)
+        compare(g, o, f"8x4 cubic{filt} {name} {sname}", tol=2e-6)
+        if gk >= 2:
+            out = ctx.filter(torch.from_numpy(np.ascontiguousarray(uv)).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(duv)).cuda(), tex, m, seed=12)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), g["out"]), f"{name} {sname}: records change the colours"
+    tex.close()
+
+
+def test_bicubic_lookup_maps_on_hardware(G):
+    """The bicubic counterpart of Figure 4 (the supplement's additional
+    bicubic results) on 8x4 waves: over rotations and magnifications the
+    GPU's per-tile success equals the oracle's for List, Mask and Box with
+    one and two texels per lane; List and Mask cover identical regions, Box
+    succeeds only where List does, and two texels per lane never succeed
+    less often than one."""
+    ctf, ctx, _ = G
+    tex = ctx.constant_texture(4096, 4096, (0.0, 0.0, 0.0, 0.0))
+    otex = O.constant_texture(4096, 4096, (0, 0, 0, 0))
+    angs = np.radians(np.repeat(np.arange(0, 90.01, 1.0), 8))
+    for filt in (1, 2):
+        for mag in (1.5, 2.0, 2.5, 3.0, 3.5, 4.5):
+            uv, duv = _quads(mag, angs, seed=int(mag * 10) + filt)
+            succ = {}
+            for k in (1, 2):
+                for gk, ok in ((2, O.LIST), (4, O.MASK), (3, O.BOX)):
+                    g = run_w32(G, uv, duv, tex, ctf.method(gk, k=k, filter=filt, wave_shape=ctf.WAVE_8X4))
+                    o = O.filter(uv, duv, otex, O.method(ok, k=k, filter=filt), tile=(8, 4))
+                    assert np.array_equal(g["stats"]["flags"], o["stats"]["flags"]), (filt, mag, k, gk)
+                    succ[(gk, k)] = (g["stats"]["flags"] & O.TILE_OK) != 0
+            for k in (1, 2):
+                assert np.array_equal(succ[(2, k)], succ[(4, k)]), (filt, mag, k)
+                assert not np.any(succ[(3, k)] & ~succ[(2, k)]), (filt, mag, k)
+            assert not np.any(succ[(2, 1)] & ~succ[(2, 2)]), (filt, mag)
     tex.close()
