@@ -179,7 +179,7 @@ typedef struct ctf_method {
     int32_t mask_side;           /* CTF_MASK: 16 */
     int32_t max_evals_per_lane;  /* k in 1..4: a wave succeeds when n <= k * |A| */
     int32_t fallback;            /* CTF_FB_STF1 / CTF_FB_C / CTF_FB_CPLUS */
-    int32_t filter;              /* CTF_FILTER_*; ctf_filter_layers takes bilinear only */
+    int32_t filter;              /* CTF_FILTER_* */
     int32_t split;               /* CTF_SPLIT_AUTO / CTF_SPLIT_OFF (procedural textures) */
     int32_t wave_shape;          /* CTF_WAVE_8X8 / CTF_WAVE_8X4 */
 } ctf_method;
@@ -248,8 +248,9 @@ ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
  * out: device float [n_layers][sh][sw][4].  tile_stats: nullable device
  * [n_layers][tiles]; debug_stf: nullable device int32 [n_layers][sh][sw][2];
  * frame_stats: nullable, totals over all layers.  Other arguments as for
- * ctf_filter.  Errors: CTF_ERR_INVALID_ARG, CTF_ERR_UNSUPPORTED (non-decoder
- * texture, mixed precisions, a filter other than CTF_FILTER_BILINEAR). */
+ * ctf_filter (every filter and fallback of ctf_filter, 8x8 waves).  Errors:
+ * CTF_ERR_INVALID_ARG, CTF_ERR_UNSUPPORTED (non-decoder texture, mixed
+ * precisions, 8x4 waves). */
 ctf_status ctf_filter_layers(ctf_context ctx, const float *uv, const float *uv_derivs,
                              int32_t sw, int32_t sh, int32_t n_layers, const ctf_texture *texs,
                              const float *xforms, const ctf_method *method, uint64_t seed,

@@ -289,8 +289,6 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_d
     if (n_layers < 1 || n_layers > 8) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: n_layers %d", n_layers);
     ctf_status st = check_method(m, "ctf_filter_layers");
     if (st != CTF_OK) return st;
-    if (m->filter != CTF_FILTER_BILINEAR)
-        return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the layered launch takes the bilinear filter only");
     if (m->wave_shape != CTF_WAVE_8X8)
         return fail(CTF_ERR_UNSUPPORTED, "ctf_filter_layers: the layered launch takes 8x8 waves only");
     for (int l = 0; l < n_layers; ++l) {

@@ -998,6 +998,93 @@ hipError_t launch_dec_p(const FilterArgs& a, const DevDecoderWeights& d, hipStre
     }
 }
 
+// Several material layers in one launch: layer l samples its own decoder at
+// uv_l = M_l uv (derivatives alike).  Layers are the outer loop so that one
+// layer's latent grids stay resident in the L2 while its tiles are walked;
+// each wave reloads the MLP weights once per layer.
+constexpr int kMaxLayers = 8;
+
+struct LayerSet {
+    DevDecoderWeights dec[kMaxLayers];
+    float xf[kMaxLayers][4];   // row-major 2x2
+    int n;
+};
+
+template <int METHOD, int P, bool STATS, bool FB, int FILTER>
+__global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>())) void
+k_filter_layers(FilterArgs a, LayerSet LS)
+{
+    __shared__ DecLds lds_all[kDecWaves];
+    const int wid = wave_in_block();
+    const int lane = lane_id();
+    DecLds& L = lds_all[wid];
+    const Band band(a.ntiles, wid);
+    const int64_t npix = (int64_t)a.sw * a.sh;
+    FrameCounters fc;
+    for (int l = 0; l < LS.n; ++l) {
+        const DevDecoderWeights& D = LS.dec[l];
+        FwdWeights<P> W;
+        W.load(D.w, lane);
+        Biases Bz;
+        Bz.load(D.bias, lane);
+        const float tex_w = (float)D.grid.tex_w;
+        const float m00 = LS.xf[l][0], m01 = LS.xf[l][1], m10 = LS.xf[l][2], m11 = LS.xf[l][3];
+        FilterArgs al = a;
+        al.out = a.out + (size_t)l * npix * 4;
+        al.tile_stats = a.tile_stats ? a.tile_stats + (size_t)l * a.ntiles : nullptr;
+        al.stf_xy = a.stf_xy ? a.stf_xy + (size_t)l * npix * 2 : nullptr;
+        al.lists = nullptr;
+        al.layer = (uint32_t)l;
+        float2 uv_next;
+        float4 d_next;
+        TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+        load_tile_px(a, next, band.end, uv_next, d_next);
+        while (next.tile < band.end) {
+            const TileWalk cur = next;
+            const float2 uv = uv_next;
+            const float4 d = d_next;
+            next.advance(band.nw);
+            load_tile_px(a, next, band.end, uv_next, d_next);
+            // layer coordinates, float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u)
+            const float lu = __builtin_fmaf(m01, uv.y, m00 * uv.x), lv = __builtin_fmaf(m11, uv.y, m10 * uv.x);
+            const float4 ld = make_float4(__builtin_fmaf(m01, d.y, m00 * d.x), __builtin_fmaf(m11, d.y, m10 * d.x),
+                                          __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
+            const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
+            dec_tile<METHOD, P, STATS, FB, FILTER>(al, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
+        }
+    }
+    if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
+}
+
+
+template <int FILTER>
+struct GoLayers {
+    template <int METHOD, int P, bool STATS, bool FB>
+    struct Go {
+        static hipError_t run(const FilterArgs& a, const LayerSet& LS, hipStream_t s)
+        {
+            const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+            auto k = k_filter_layers<METHOD, P, STATS, FB, FILTER>;
+            const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
+            return hipGetLastError();
+        }
+    };
+};
+
+template <int P, int FILTER>
+hipError_t launch_layers_p(const FilterArgs& a, const LayerSet& LS, hipStream_t s)
+{
+    switch (a.method) {
+    case CTF_BILINEAR4: return dispatch_flags<CTF_BILINEAR4, P, GoLayers<FILTER>::template Go>(a, LS, s);
+    case CTF_STF1: return dispatch_flags<CTF_STF1, P, GoLayers<FILTER>::template Go>(a, LS, s);
+    case CTF_LIST: return dispatch_flags<CTF_LIST, P, GoLayers<FILTER>::template Go>(a, LS, s);
+    case CTF_BOX: return dispatch_flags<CTF_BOX, P, GoLayers<FILTER>::template Go>(a, LS, s);
+    case CTF_MASK: return dispatch_flags<CTF_MASK, P, GoLayers<FILTER>::template Go>(a, LS, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace dec
 
 }  // namespace ctf

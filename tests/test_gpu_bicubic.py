@@ -150,13 +150,45 @@ def test_bicubic_decoder_collaborative_equals_full_bitwise(G, fname, flt):
     dec.close()
 
 
-def test_bicubic_rejected_on_layered_launch(G):
+@pytest.mark.parametrize("records", [True, False], ids=["records", "no_records"])
+@pytest.mark.parametrize("fname,filt", [("bspline", 1), ("catmull_rom", 2)])
+@pytest.mark.parametrize("gk,ok,k", [(2, O.LIST, 4), (4, O.MASK, 2), (0, O.BILINEAR4, 1)])
+def test_bicubic_layered_launch_matches_oracle_per_layer(G, fname, filt, gk, ok, k, records):
+    """The layered launch with the cubic filters: every layer against the
+    oracle on its own GPU-decoded lattice and transform."""
+    from test_gpu_filter import STAT_FIELDS, _edge_scene
     ctf, ctx, torch = G
-    dec = ctx.decoder(16, 4, 64, 64, cs.decoder_init(16, 4, 64, seed=1))
-    tex = ctx.decoder_texture(dec, 0)
-    sc = cs.tilted_plane_scene()
-    with pytest.raises(ctf.CtfError, match="bilinear"):
-        ctx.filter_layers(torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda(), [tex],
-                          np.eye(2, dtype=np.float32)[None], ctf.method(ctf.LIST, filter=ctf.FILTER_BSPLINE))
-    tex.close()
-    dec.close()
+    n = 2
+    decs = [ctx.decoder(16, 4, 64, 64, cs.decoder_init(16, 4, 64, seed=60 + i, latent_range=0.5)) for i in range(n)]
+    texs = [ctx.decoder_texture(d, 0) for d in decs]
+    ys, xs = np.mgrid[0:64, 0:64]
+    lattice = torch.from_numpy(np.stack([xs.ravel(), ys.ravel()], -1).astype(np.int32)).cuda()
+    tables = [t.eval(lattice).cpu().numpy().reshape(64, 64, 4) for t in texs]
+    xf = np.array([[[1.3, -0.4], [0.4, 1.3]], [[0.6, 0.2], [-0.2, 0.6]]], np.float32)
+    for uv, duv in ((cs.tilted_plane_scene().uv, cs.tilted_plane_scene().duv), _edge_scene()):
+        sh, sw = uv.shape[:2]
+        tiles = ((sw + 7) // 8) * ((sh + 7) // 8)
+        ts = torch.zeros((n, tiles, 128), dtype=torch.uint8, device="cuda")
+        sx = torch.full((n, sh, sw, 2), -2**31, dtype=torch.int32, device="cuda")
+        fs = ctf.frame_stats_buffer()
+        out = ctx.filter_layers(torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), texs, xf,
+                                ctf.method(gk, k=k, filter=filt), seed=9, tile_stats=ts if records else None,
+                                frame_stats=fs, stf=sx)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+        evals = 0
+        for l in range(n):
+            o = O.filter(uv, duv, O.table_texture(tables[l]), O.method(ok, k=k, filter=filt), seed=9, layer=l,
+                         xform=xf[l], stf=True)
+            if records:
+                st = ctf.tile_stats_numpy(ts[l])
+                for f in STAT_FIELDS:
+                    assert np.array_equal(st[f], o["stats"][f]), (l, f)
+            assert np.array_equal(sx[l].cpu().numpy(), o["stf"]), l
+            assert np.abs(out[l] - o["out"]).max() <= TOL_CUBIC, l
+            evals += int(o["stats"]["evals"].sum())
+        assert ctf.frame_stats_dict(fs)["evals"] == evals
+    for t in texs:
+        t.close()
+    for d in decs:
+        d.close()
