@@ -97,8 +97,9 @@ enum { CTF_SPLIT_AUTO = 0, CTF_SPLIT_OFF = 1 };
  * CTF_WAVE_8X4: the paper's 8x4-pixel tiles of 32 lanes (Section 3), two per
  * wave64, each half-wave taking its own collaborative step; tiles are then
  * 8x4, numbered row-major over ceil(sw/8) x ceil(sh/4) (tile records and
- * lists per 8x4 tile).  8x4 supports the bilinear and bicubic filters, the
- * one-tap fallback and the procedural / table producers. */
+ * lists per 8x4 tile).  8x4 supports every filter and fallback (C+ spreads
+ * the spare lanes of a 32-lane tile, Eq. 2 as written) with the procedural /
+ * table producers. */
 enum { CTF_WAVE_8X8 = 0, CTF_WAVE_8X4 = 1 };
 
 /* Texel producers (Section 3: "produce a texel"). */

@@ -242,8 +242,6 @@ static ctf_status check_method(const ctf_method* m, const char* who)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown split mode %d", who, m->split);
     if (m->wave_shape != CTF_WAVE_8X8 && m->wave_shape != CTF_WAVE_8X4)
         return fail(CTF_ERR_INVALID_ARG, "%s: unknown wave shape %d", who, m->wave_shape);
-    if (m->wave_shape == CTF_WAVE_8X4 && m->fallback != CTF_FB_STF1)
-        return fail(CTF_ERR_UNSUPPORTED, "%s: 8x4 waves take the one-tap fallback", who);
     return CTF_OK;
 }
 

@@ -12,6 +12,7 @@
 // 16-lane rows) and each lane selects its own half's value.
 #include "ctf_device.h"
 #include "ctf_internal.h"
+#include "fallback.h"
 
 namespace ctf {
 
@@ -25,8 +26,10 @@ struct W32Lds {
     float4 vals[2][kHalfItems];   // produced texel values, by half and item
     uint64_t keys[kWave * F * F]; // List past 16x16: sorted unique keys, half in bit 62
     uint16_t items[2][256];       // Mask: item i -> position t = h(i, B)
-    uint8_t rank[2][256];         // Mask: position t -> item index h^-1(t, B)
+    uint8_t rank[2][256];         // Mask: position t -> item index h^-1(t, B); fallback: slot + 1
     uint8_t bytes[2][256];        // footprint-corner scatter before the ballots
+    StashEntry stash[2][32];      // fallback C+: each lane's footprint, by half
+    int2 produced[2][32];         // fallback C past 16x16: the produced texels, by slot
 };
 
 // min/max over each half-wave (all 64 lanes active): DPP over the 16-lane
@@ -105,12 +108,180 @@ __device__ __forceinline__ int w32_find(const W32Lds<F>& L, int lo, int hi, uint
     return lo;
 }
 
+// Fallbacks C and C+ (Section 3.4, Eq. 1 and Eq. 2) per half-wave: the
+// wave64 planning of fallback.h with every ballot, rank and table taken over
+// the lanes of one 8x4 tile, so Eq. 2 spreads the spare lanes of a 32-lane
+// wave as the paper writes it.  `fbl`: this lane's half takes the fallback.
+struct W32Fallback {
+    bool produces;
+    int2 texel;
+    int slot;
+    bool table;
+};
+
+template <int FILTER, int F>
+__device__ W32Fallback plan_fallback_w32(W32Lds<F>& L, int fb, bool fbl, bool inA, int h, int nA, int rankA,
+                                         const Footprint& f, int2 pick, uint32_t h3, bool fits16, int xmin, int ymin,
+                                         uint64_t Hm, int& nprod0, int& nprod1)
+{
+    const int lane = lane_id(), ll = lane & 31;
+    const bool mine = fbl && inA;
+    W32Fallback P;
+    P.produces = mine;
+    P.texel = pick;
+    P.table = fits16;
+    if (fb == CTF_FB_CPLUS && ballot(fbl && fits16) != 0) {
+        const bool cplus = fbl && fits16;
+        reinterpret_cast<uint32_t*>(L.bytes)[lane] = 0u;
+        reinterpret_cast<uint32_t*>(L.bytes)[kWave + lane] = 0u;
+        L.stash[h][ll] = StashEntry{f.x0, f.y0, f.s, f.t};
+        wave_lds_sync();
+        if (mine && cplus) L.bytes[h][16 * (pick.y - ymin) + (pick.x - xmin)] = 1;
+        wave_lds_sync();
+        // S per half: the distinct drawn texels of its lanes of A
+        uint64_t S0[4], S1[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t b0 = ballot(L.bytes[h][64 * w + ll] != 0);
+            const uint64_t b1 = ballot(L.bytes[h][64 * w + 32 + ll] != 0);
+            S0[w] = (uint64_t)lo32(b0) | ((uint64_t)lo32(b1) << 32);
+            S1[w] = (uint64_t)hi32(b0) | ((uint64_t)hi32(b1) << 32);
+        }
+        int ns0 = 0, ns1 = 0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const uint64_t* Sh = hh ? S1 : S0;
+            int base = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if ((Sh[w] >> lane) & 1u) L.items[hh][base + mbcnt(Sh[w])] = (uint16_t)(64 * w + lane);
+                base += popc64(Sh[w]);
+            }
+            if (hh) ns1 = base;
+            else ns0 = base;
+        }
+        wave_lds_sync();
+        // lane of each rank of A in its half (the bytes are free after the ballots)
+        if (inA) L.bytes[h][rankA] = (uint8_t)ll;
+        wave_lds_sync();
+        if (mine && cplus) {
+            const int ns = h ? ns1 : ns0;
+            P.produces = false;
+            if (rankA < ns) {
+                const int t = L.items[h][rankA];
+                P.produces = true;
+                P.texel = make_int2(xmin + (t & 15), ymin + (t >> 4));
+            } else {
+                constexpr int O = Taps<FILTER>::O;
+                const StashEntry T = L.stash[h][L.bytes[h][cplus_target(nA, ns, rankA)]];
+                float wx[4], wy[4];
+                taps32<FILTER>(T.s, wx);
+                taps32<FILTER>(T.t, wy);
+                const int ox = T.x0 - O, oy = T.y0 - O;
+                // candidates: taps (row-major) with a nonzero weight, not in S
+                uint32_t cand = 0u;
+                float wsum = 0.f;
+#pragma unroll
+                for (int q = 0; q < F * F; ++q) {
+                    const float wq = wx[q % F] * wy[q / F];
+                    const int tq = 16 * (oy + q / F - ymin) + (ox + q % F - xmin);
+                    const uint64_t Sw = h ? S1[tq >> 6] : S0[tq >> 6];
+                    if (wq != 0.0f && !((Sw >> (tq & 63)) & 1u)) {
+                        cand |= 1u << q;
+                        wsum += __builtin_fabsf(wq);
+                    }
+                }
+                if (cand) {
+                    const float thr = (float)(h3 >> 8) * 0x1p-24f * wsum;
+                    float run = 0.f;
+                    int pq = -1;
+                    bool done = false;
+#pragma unroll
+                    for (int q = 0; q < F * F; ++q) {
+                        if (!((cand >> q) & 1u) || done) continue;
+                        pq = q;
+                        run += __builtin_fabsf(wx[q % F] * wy[q / F]);
+                        done = run > thr;
+                    }
+                    P.produces = true;
+                    P.texel = make_int2(ox + pq % F, oy + pq / F);
+                }
+            }
+        }
+    }
+    const uint64_t prod = ballot(P.produces);
+    nprod0 = __popc(lo32(prod));
+    nprod1 = __popc(hi32(prod));
+    P.slot = mbcnt(prod & Hm);
+    // slot table of the fallback halves (the other half keeps its rank table)
+    if (fbl && fits16) {
+        reinterpret_cast<uint32_t*>(L.rank[h])[ll] = 0u;
+        reinterpret_cast<uint32_t*>(L.rank[h])[32 + ll] = 0u;
+    }
+    wave_lds_sync();
+    if (P.produces) {
+        if (P.table) L.rank[h][16 * (P.texel.y - ymin) + (P.texel.x - xmin)] = (uint8_t)(P.slot + 1);
+        else L.produced[h][P.slot] = P.texel;
+    }
+    wave_lds_sync();
+    return P;
+}
+
+// Eq. 1 for a lane of A of a fallback half (fallback_color of fallback.h over
+// this half's slots).
+template <int FILTER, int F>
+__device__ float4 fallback_color_w32(const W32Lds<F>& L, const W32Fallback& P, int h, int nprod, const Footprint& f,
+                                     int2 pick, int xmin, int ymin)
+{
+    constexpr int O = Taps<FILTER>::O;
+    float wx[4], wy[4];
+    taps32<FILTER>(f.s, wx);
+    taps32<FILTER>(f.t, wy);
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), sum = acc;
+    float wsum = 0.f;
+    int N = 0, own = 0;
+#pragma unroll
+    for (int q = 0; q < F * F; ++q) {
+        const int x = f.x0 - O + q % F, y = f.y0 - O + q / F;
+        const float wq = wx[q % F] * wy[q / F];
+        int slot = -1;
+        if (P.table) {
+            slot = (int)L.rank[h][16 * (y - ymin) + (x - xmin)] - 1;
+        } else {
+            for (int r = 0; r < nprod; ++r) {
+                const int2 e = L.produced[h][r];
+                if (e.x == x && e.y == y) {
+                    slot = r;
+                    break;
+                }
+            }
+        }
+        if (x == pick.x && y == pick.y) own = slot;
+        if (slot < 0 || wq == 0.0f) continue;
+        const float4 v = L.vals[h][slot];
+        acc.x = __builtin_fmaf(wq, v.x, acc.x);
+        acc.y = __builtin_fmaf(wq, v.y, acc.y);
+        acc.z = __builtin_fmaf(wq, v.z, acc.z);
+        acc.w = __builtin_fmaf(wq, v.w, acc.w);
+        sum.x += v.x;
+        sum.y += v.y;
+        sum.z += v.z;
+        sum.w += v.w;
+        wsum += wq;
+        ++N;
+    }
+    if (N == 0) return L.vals[h][own];
+    const float inv = 1.0f / (float)N, rest = 1.0f - wsum;
+    return make_float4(__builtin_fmaf(rest, sum.x * inv, acc.x), __builtin_fmaf(rest, sum.y * inv, acc.y),
+                       __builtin_fmaf(rest, sum.z * inv, acc.z), __builtin_fmaf(rest, sum.w * inv, acc.w));
+}
+
 struct HalfDecision {
     int n, unique;
     bool cap_ok, count_ok, success;
 };
 
-template <int METHOD, int TEX, bool STATS, int FILTER>
+template <int METHOD, int TEX, bool STATS, int FILTER, bool FB>
 __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, DevTexture T)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
@@ -279,10 +450,20 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         // ---- production: each lane evaluates at most one texel per round
         float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
         int2 pick = make_int2(INT32_MIN, INT32_MIN);
+        uint32_t h1 = 0, h2 = 0;
         if (draws) {
-            uint32_t h1, h2;
             stf_hashes(a.seed, a.layer, px, py, h1, h2);
             pick = stf_pick_filter<FILTER>(f, h1, h2);
+        }
+        // fallback C / C+ for the lanes of A of a failed half
+        bool fbl = false;
+        W32Fallback P{};
+        int nprod0 = 0, nprod1 = 0;
+        if constexpr (FB && kCollab) {
+            fbl = !success && nA > 0;
+            if (ballot(fbl) != 0)
+                P = plan_fallback_w32<FILTER, F>(L, a.fallback, fbl, inA, h, nA, rankA, f, pick, pcg_hash(h2), fits16,
+                                                  xmin, ymin, Hm, nprod0, nprod1);
         }
         if constexpr (METHOD == CTF_BILINEAR4) {
             if (exact) {
@@ -308,7 +489,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
             for (int round = 0; round < (kCollab ? k : 1); ++round) {
                 const int item = rankA + round * nA;
                 const bool produce = kCollab && success && inA && item < n;
-                const bool draw_now = draws && round == 0;
+                const bool draw_now = draws && round == 0 && !(fbl && inA);
                 if (ballot(produce || draw_now) == 0) break;
                 int ex = pick.x, ey = pick.y;
                 if (produce) {
@@ -333,6 +514,12 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                     if (produce) L.vals[h][item] = v;
                     if (draw_now) res = v;
                 }
+            }
+            if constexpr (FB && kCollab) {
+                // the fallback halves' planned texels, then Eq. 1
+                if (fbl && inA && P.produces) L.vals[h][P.slot] = texel_eval<TEX>(T, P.texel.x, P.texel.y);
+                wave_lds_sync();
+                if (fbl && inA) res = fallback_color_w32<FILTER, F>(L, P, h, h ? nprod1 : nprod0, f, pick, xmin, ymin);
             }
             if constexpr (kCollab) {
                 wave_lds_sync();
@@ -381,6 +568,8 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             if constexpr (METHOD == CTF_BILINEAR4) evals[hh] = F * F * __popc(actm[hh]);
+            else if (FB && kCollab && !D[hh].success && __popc(Am[hh]) > 0)
+                evals[hh] = (hh ? nprod1 : nprod0) + __popc(stfm[hh] & ~Am[hh]);
             else evals[hh] = (D[hh].success ? D[hh].n : 0) + __popc(stfm[hh]);
         }
         if (ll == 0 && tile_ok && a.tile_stats) {
@@ -421,12 +610,15 @@ hipError_t launch_w32_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t 
     const int64_t npairs = (a.ntiles + 1) / 2;
     int64_t blocks = (npairs + kW32Waves - 1) / kW32Waves;
     if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
-    if (a.tile_stats)
-        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0,
-                           s, a, T);
-    else
-        hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER>), dim3((unsigned)blocks), dim3(kWave * kW32Waves), 0,
-                           s, a, T);
+    const dim3 grid((unsigned)blocks), block(kWave * kW32Waves);
+    constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    if (kCollab && a.fallback != CTF_FB_STF1) {
+        if (a.tile_stats) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
+        else hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER, kCollab>), grid, block, 0, s, a, T);
+    } else {
+        if (a.tile_stats) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
+        else hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER, false>), grid, block, 0, s, a, T);
+    }
     return hipGetLastError();
 }
 

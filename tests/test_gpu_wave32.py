@@ -105,16 +105,45 @@ def test_figure4_thresholds_on_hardware(G):
     tex.close()
 
 
-def test_wave32_shape_rejects_unbuilt_combinations(G):
+def test_wave32_shape_rejects_the_decoder_producer(G):
     ctf, ctx, torch = G
     sc = cs.tilted_plane_scene()
+    dec = ctx.decoder(16, 4, 64, 64, cs.decoder_init(16, 4, 64, seed=1))
+    tex = ctx.decoder_texture(dec, 0)
+    uv, duv = torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda()
+    with pytest.raises(ctf.CtfError, match="8x4"):
+        ctx.filter(uv, duv, tex, ctf.method(ctf.LIST, wave_shape=ctf.WAVE_8X4))
+    tex.close()
+    dec.close()
+
+
+FALLBACKS = [("list_C", 2, O.LIST, (0, 0), 1, 1), ("list_Cplus", 2, O.LIST, (0, 0), 1, 2),
+             ("mask_Cplus", 4, O.MASK, (0, 0), 1, 2), ("box4x4_C", 3, O.BOX, (4, 4), 1, 1),
+             ("box4x4_Cplus", 3, O.BOX, (4, 4), 1, 2), ("mask_k2_Cplus", 4, O.MASK, (0, 0), 2, 2)]
+
+
+@pytest.mark.parametrize("filt", [0, 1], ids=["bilinear", "bspline"])
+@pytest.mark.parametrize("name,gk,ok,box,k,fb", FALLBACKS)
+def test_wave32_shape_fallbacks(G, filt, name, gk, ok, box, k, fb):
+    """Fallbacks C and C+ on 8x4 waves (Eq. 2 over the 32 lanes of a tile)
+    against the oracle with 8x4 tiles: records, draws and counts exact,
+    colours within 1e-6 (2e-6 bicubic); the fallback runs on many tiles."""
+    from test_gpu_filter import compare
+    ctf, ctx, _ = G
     pqj, amp = cs.sinusoid_params(64, 8, 8, seed=8)
     tex = ctx.sinusoid_texture(64, pqj, amp)
-    uv, duv = torch.from_numpy(sc.uv).cuda(), torch.from_numpy(sc.duv).cuda()
-    for m in (ctf.method(ctf.LIST, fallback=ctf.FB_C, wave_shape=ctf.WAVE_8X4),
-              ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS, filter=ctf.FILTER_BSPLINE, wave_shape=ctf.WAVE_8X4)):
-        with pytest.raises(ctf.CtfError, match="8x4"):
-            ctx.filter(uv, duv, tex, m)
+    otex = O.sinusoid_texture(64, pqj, amp)
+    scenes = _scenes() + [("quads_low", cs.lowmag_quads_scene(200, seed=5, tex_w=64, mag=(0.6, 2.0)))]
+    failed = 0
+    for sname, (uv, duv) in scenes:
+        m = ctf.method(gk, box=box, k=k, fallback=fb, filter=filt, wave_shape=ctf.WAVE_8X4)
+        g = run_w32(G, uv, duv, tex, m, seed=12)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box, k=k, fallback=fb, filter=filt), seed=12, tile=(8, 4),
+                     lists=True, stf=True)
+        compare(g, o, f"8x4 {name} f{filt} {sname}", tol=2e-6 if filt else 1e-6)
+        st = o["stats"]
+        failed += int(((st["part"] != 0) & ((st["flags"] & O.TILE_OK) == 0)).sum())
+    assert failed > 50, failed
     tex.close()
 
 
