@@ -157,7 +157,8 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                     ("bilinear4_8x4", ctf.method(ctf.BILINEAR4, wave_shape=ctf.WAVE_8X4)),
                     ("list_8x4", ctf.method(ctf.LIST, wave_shape=ctf.WAVE_8X4)),
                     ("box4x4_8x4", ctf.method(ctf.BOX, box=(4, 4), wave_shape=ctf.WAVE_8X4)),
-                    ("mask_8x4", ctf.method(ctf.MASK, wave_shape=ctf.WAVE_8X4))):
+                    ("mask_8x4", ctf.method(ctf.MASK, wave_shape=ctf.WAVE_8X4)),
+                    ("mask_fbCplus_8x4", ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS, wave_shape=ctf.WAVE_8X4))):
         fs = ctf.frame_stats_buffer()
         ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs)
         torch.cuda.synchronize()
