@@ -230,8 +230,8 @@ typedef struct ctf_frame_stats {
  *   (y, x)-ascending); debug_stf: nullable device int32 [sh][sw][2], the
  *   one-tap texel drawn by each pixel not filtered exactly (also those of
  *   fallback C / C+) and INT32_MIN for the other active pixels.
- * Errors: CTF_ERR_INVALID_ARG (NULL buffers, non-positive sizes, bad method),
- * CTF_ERR_UNSUPPORTED (method/texture combination not built). */
+ * Errors: CTF_ERR_INVALID_ARG (NULL buffers, sw or sh outside 1..2^24, bad
+ * method), CTF_ERR_UNSUPPORTED (method/texture combination not built). */
 ctf_status ctf_filter(ctf_context ctx, const float *uv, const float *uv_derivs,
                       int32_t sw, int32_t sh, ctf_texture tex, const ctf_method *method,
                       uint64_t seed, float *out, ctf_tile_stats *tile_stats,

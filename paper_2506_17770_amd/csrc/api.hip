@@ -60,6 +60,11 @@ struct DeviceScope {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Screen sides up to 2^24: a lane's pixel offset inside its tile (up to
+// 7 rows of the screen, 16 bytes a pixel) then fits the kernels' 32-bit
+// offsets, and pixel coordinates stay far from int32 overflow.
+constexpr int32_t kMaxScreenSide = 1 << 24;
+
 }  // namespace
 
 // decoder.hip / filter_decoder.hip
@@ -283,7 +288,8 @@ ctf_status ctf_filter_layers(ctf_context ctx, const float* uv, const float* uv_d
     set_error("");
     if (!ctx || !uv || !uv_derivs || !texs || !xforms || !m || !out)
         return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: NULL argument");
-    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: screen %d x %d", sw, sh);
+    if (sw <= 0 || sh <= 0 || sw > kMaxScreenSide || sh > kMaxScreenSide)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: screen %d x %d (sides 1..2^24)", sw, sh);
     if (n_layers < 1 || n_layers > 8) return fail(CTF_ERR_INVALID_ARG, "ctf_filter_layers: n_layers %d", n_layers);
     ctf_status st = check_method(m, "ctf_filter_layers");
     if (st != CTF_OK) return st;
@@ -313,7 +319,8 @@ ctf_status ctf_filter(ctf_context ctx, const float* uv, const float* uv_derivs, 
     set_error("");
     if (!ctx || !uv || !uv_derivs || !tex || !m || !out)
         return fail(CTF_ERR_INVALID_ARG, "ctf_filter: NULL argument");
-    if (sw <= 0 || sh <= 0) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: screen %d x %d", sw, sh);
+    if (sw <= 0 || sh <= 0 || sw > kMaxScreenSide || sh > kMaxScreenSide)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_filter: screen %d x %d (sides 1..2^24)", sw, sh);
     ctf_status st = check_method(m, "ctf_filter");
     if (st != CTF_OK) return st;
     if (tex->ctx != ctx) return fail(CTF_ERR_INVALID_ARG, "ctf_filter: texture from another context");

@@ -35,25 +35,32 @@ hipError_t launch_texel_eval_simt(const DevTexture& T, const int32_t* xy, int64_
 {
     if (n <= 0) return hipSuccess;
     const int bs = 256;
-    const dim3 grid((unsigned)((n + bs - 1) / bs));
-    const int2* p = reinterpret_cast<const int2*>(xy);
-    float4* o = reinterpret_cast<float4*>(out);
-    switch (T.kind) {
-    case CTF_TEX_SINUSOIDS:
-        hipLaunchKernelGGL(k_texel_eval<CTF_TEX_SINUSOIDS>, grid, dim3(bs), 0, s, T, p, n, o);
-        break;
-    case CTF_TEX_AFFINE:
-        hipLaunchKernelGGL(k_texel_eval<CTF_TEX_AFFINE>, grid, dim3(bs), 0, s, T, p, n, o);
-        break;
-    case CTF_TEX_CONSTANT:
-        hipLaunchKernelGGL(k_texel_eval<CTF_TEX_CONSTANT>, grid, dim3(bs), 0, s, T, p, n, o);
-        break;
-    case CTF_TEX_TABLE:
-        hipLaunchKernelGGL(k_texel_eval<CTF_TEX_TABLE>, grid, dim3(bs), 0, s, T, p, n, o);
-        break;
-    default: return hipErrorInvalidValue;
+    // one launch per 2^30 points keeps the grid's work-item count within 32 bits
+    constexpr int64_t kChunk = int64_t(1) << 30;
+    for (int64_t off = 0; off < n; off += kChunk) {
+        const int64_t m = n - off < kChunk ? n - off : kChunk;
+        const dim3 grid((unsigned)((m + bs - 1) / bs));
+        const int2* p = reinterpret_cast<const int2*>(xy) + off;
+        float4* o = reinterpret_cast<float4*>(out) + off;
+        switch (T.kind) {
+        case CTF_TEX_SINUSOIDS:
+            hipLaunchKernelGGL(k_texel_eval<CTF_TEX_SINUSOIDS>, grid, dim3(bs), 0, s, T, p, m, o);
+            break;
+        case CTF_TEX_AFFINE:
+            hipLaunchKernelGGL(k_texel_eval<CTF_TEX_AFFINE>, grid, dim3(bs), 0, s, T, p, m, o);
+            break;
+        case CTF_TEX_CONSTANT:
+            hipLaunchKernelGGL(k_texel_eval<CTF_TEX_CONSTANT>, grid, dim3(bs), 0, s, T, p, m, o);
+            break;
+        case CTF_TEX_TABLE:
+            hipLaunchKernelGGL(k_texel_eval<CTF_TEX_TABLE>, grid, dim3(bs), 0, s, T, p, m, o);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace ctf

@@ -65,3 +65,21 @@ def test_decoder_create_validates_sizes_before_the_device():
         st = ctf.lib.ctf_decoder_create(dummy_ctx, ctypes.byref(d), init.ctypes.data, ctypes.byref(h))
         assert st == want, (fields, st, ctf.lib.ctf_last_error())
         assert ctf.lib.ctf_last_error()
+
+
+def test_filter_validates_screen_sides_before_the_device():
+    """Screen sides outside 1..2^24 are rejected before the context, the
+    texture or any buffer is touched (dummy handles and pointers)."""
+    import paper_2506_17770_amd as ctf
+    dummy = ctypes.c_void_p(1)
+    m = ctf.method(ctf.LIST)
+    xf = (ctypes.c_float * 4)(1, 0, 0, 1)
+    texs = (ctypes.c_void_p * 1)(1)
+    for sw, sh in [((1 << 24) + 1, 8), (8, (1 << 24) + 1), (0, 8), (8, -1)]:
+        st = ctf.lib.ctf_filter(dummy, dummy, dummy, sw, sh, dummy, ctypes.byref(m), 0, dummy, None, None,
+                                None, None, None)
+        assert st == 1, (sw, sh, st)
+        assert b"screen" in ctf.lib.ctf_last_error()
+        st = ctf.lib.ctf_filter_layers(dummy, dummy, dummy, sw, sh, 1, texs, xf, ctypes.byref(m), 0, dummy,
+                                       None, None, None, None)
+        assert st == 1, (sw, sh, st)
