@@ -818,6 +818,7 @@ ctf_status ctf_decoder_get_params(ctf_decoder d, float* host, size_t count)
     if (!d || !host || count != (size_t)d->lay.total)
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_get_params: bad arguments or count");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_get_params: set device");
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(host, d->master, count * 4, hipMemcpyDeviceToHost);
     return e == hipSuccess ? CTF_OK : hip_fail(e, "ctf_decoder_get_params");
@@ -829,6 +830,7 @@ ctf_status ctf_decoder_set_params(ctf_decoder d, const float* host, size_t count
     if (!d || !host || count != (size_t)d->lay.total)
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_set_params: bad arguments or count");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_set_params: set device");
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(d->master, host, count * 4, hipMemcpyHostToDevice);
     d->lp_precision = -1;
@@ -847,6 +849,7 @@ ctf_status ctf_decoder_get_state(ctf_decoder d, void* host, size_t bytes)
     if (!d || !host || bytes != ctf_decoder_state_bytes(d))
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_get_state: bad arguments or size");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_get_state: set device");
     char* p = static_cast<char*>(host);
     const int64_t hdr[2] = {d->step, d->lay.total};
     std::memcpy(p, hdr, 16);
@@ -868,6 +871,7 @@ ctf_status ctf_decoder_set_state(ctf_decoder d, const void* host, size_t bytes)
     std::memcpy(hdr, p, 16);
     if (hdr[1] != d->lay.total || hdr[0] < 0) return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_set_state: blob mismatch");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_set_state: set device");
     const size_t n = (size_t)d->lay.total * 4;
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(d->master, p + 16, n, hipMemcpyHostToDevice);
@@ -887,6 +891,7 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder d, const int32_t* xy, const float* 
     if (precision != CTF_BF16 && precision != CTF_FP16)
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_loss_grad: precision");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_loss_grad: set device");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = ensure_batch(d, n);
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
@@ -905,10 +910,13 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
     if (precision != CTF_BF16 && precision != CTF_FP16)
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_train: precision");
     const DevTexture& T = target->dev;
+    if (target->ctx->device != d->ctx->device)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_train: target texture on another device");
     if (T.kind == CTF_TEX_DECODER) return fail(CTF_ERR_UNSUPPORTED, "ctf_decoder_train: decoder targets not built");
     if (T.width != d->desc.tex_w || T.height != d->desc.tex_w)
         return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_train: target size differs from the decoder's tex_w");
     DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_train: set device");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = ensure_batch(d, batch);
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
@@ -954,6 +962,8 @@ ctf_status ctf_internal_decoder_texture(ctf_texture t)
 {
     ctf_decoder d = t->desc.decoder;
     const int prec = t->desc.precision;
+    if (d->ctx->device != t->ctx->device)
+        return fail(CTF_ERR_INVALID_ARG, "decoder texture: the decoder lives on another device");
     if (t->desc.width != d->desc.tex_w || t->desc.height != d->desc.tex_w)
         return fail(CTF_ERR_INVALID_ARG, "decoder texture: width/height must equal the decoder's tex_w");
     std::vector<float> P((size_t)d->lay.total);
