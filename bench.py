@@ -101,8 +101,22 @@ def timed(fn, stream, steps, warmup, torch):
     return wall, per
 
 
-def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed):
-    """Oracle (float64 decoder, List k=4) on a bounded sample of tiles, all host threads."""
+def tile_run_segments(b, count, tiles_x, width, height):
+    """Pixel slices (rows, cols) of tiles b .. b+count-1 (row-major tiles)."""
+    segs = []
+    t = b
+    while t < b + count:
+        ty, tx0 = divmod(t, tiles_x)
+        tx1 = min(tiles_x, tx0 + (b + count - t))
+        segs.append((slice(8 * ty, min(height, 8 * ty + 8)), slice(8 * tx0, min(width, 8 * tx1))))
+        t += tx1 - tx0
+    return segs
+
+
+def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed, gpu_out=None):
+    """Oracle (float64 decoder, List k=4) on a bounded sample of tiles, all host
+    threads; with ``gpu_out`` also the GPU frame's error against it on that
+    sample (compared after the timed region)."""
     import oracle as O
     tiles_x = (sc.width + 7) // 8
     ntiles = tiles_x * ((sc.height + 7) // 8)
@@ -118,21 +132,41 @@ def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed):
     starts = np.sort(rng.choice(ntiles // 64, size=max(1, n_sample // 64), replace=False)) * 64
     chunks = np.array_split(starts, threads)
 
-    def work(ch):
+    kept = [[] for _ in chunks]
+
+    def work(i, ch):
         for b in ch:
-            O.filter(sc.uv, sc.duv, otex, meth, seed=seed, tiles=(int(b), int(b) + 64), stats=False)
+            o = O.filter(sc.uv, sc.duv, otex, meth, seed=seed, tiles=(int(b), int(b) + 64), stats=False)
+            if gpu_out is not None:
+                kept[i].append([(sl, o["out"][sl]) for sl in tile_run_segments(int(b), 64, tiles_x, sc.width,
+                                                                                 sc.height)])
 
     t0 = time.perf_counter()
-    ths = [threading.Thread(target=work, args=(c,)) for c in chunks if len(c)]
+    ths = [threading.Thread(target=work, args=(i, c)) for i, c in enumerate(chunks) if len(c)]
     for t in ths:
         t.start()
     for t in ths:
         t.join()
     dt = time.perf_counter() - t0
     px = len(starts) * 64 * 64
-    return {"value": px / dt / 1e9, "unit": "Gpixels/s", "cores": len(ths), "kind": "oracle",
+    base = {"value": px / dt / 1e9, "unit": "Gpixels/s", "cores": len(ths), "kind": "oracle",
             "sample": f"{len(starts) * 64} of {ntiles} 8x8 tiles of the same frame (runs of 64 tiles), "
                       f"float64 decoder, List k=4 + STF, {dt:.1f} s wall"}
+    if gpu_out is None:
+        return base, None
+    mx, se, n = 0.0, 0.0, 0
+    for runs in kept:
+        for segs in runs:
+            for sl, ref in segs:
+                d = gpu_out[sl].astype(np.float64) - ref
+                mx = max(mx, float(np.abs(d).max()))
+                se += float((d * d).sum())
+                n += d.size
+    mse = se / max(1, n)
+    err = {"max_abs": mx, "psnr_db": 10 * math.log10(1.0 / mse) if mse > 0 else None, "values": n,
+           "reference": "the oracle's frame on the same sample: float64 decoder from the same float32 "
+                        "master parameters, float64 filtering; the GPU decodes in fp16 MFMA"}
+    return base, err
 
 
 def bench_procedural(ctx, ctf, cs, torch, args, stream):
@@ -334,6 +368,7 @@ def main():
     run_col = lambda: ctx.filter(uv, duv, dtex, m_col, seed=seed_stf, out=out)
     run_b4 = lambda: ctx.filter(uv, duv, dtex, m_b4, seed=seed_stf, out=out)
     wall_col, per_col = timed(run_col, stream, args.steps, args.warmup, torch)
+    col_out = out.cpu().numpy()   # the collaborative frame, for the error against the oracle
     wall_b4, per_b4 = timed(run_b4, stream, args.steps, args.warmup, torch)
     ms_col = float(np.mean(per_col))
     ms_b4 = float(np.mean(per_b4))
@@ -401,7 +436,8 @@ def main():
         res["layers_4k"] = bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
-        res["cpu_baseline"] = cpu_baseline(args, sc, dec.params(), l0, l1, H, tex_w, seed_stf)
+        res["cpu_baseline"], res["frame_error_vs_fp64_oracle"] = cpu_baseline(
+            args, sc, dec.params(), l0, l1, H, tex_w, seed_stf, gpu_out=col_out)
     print(json.dumps(res), flush=True)
 
 
