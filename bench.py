@@ -203,6 +203,17 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                      "texel_evals_per_pixel": st["evals"] / npx,
                      "not_exact_fraction": st["stf"] / max(1, st["active"]),
                      "waves_failed": st["tiles_fail"], "waves_ok": st["tiles_ok"]}
+    # the dedup machinery's own cost: the same frame on a constant texture,
+    # whose texel evaluation is free (time per Mpixel, as the paper states it)
+    ctex = ctx.constant_texture(2048, 2048, (0.25, 0.5, 0.75, 1.0))
+    overhead = {}
+    for name, m in (("bilinear4", ctf.method(ctf.BILINEAR4)), ("stf1", ctf.method(ctf.STF1)),
+                    ("list", ctf.method(ctf.LIST)), ("box4x4", ctf.method(ctf.BOX, box=(4, 4))),
+                    ("box6x6", ctf.method(ctf.BOX, box=(6, 6))), ("mask", ctf.method(ctf.MASK))):
+        _, per = timed(lambda: ctx.filter(uv, duv, ctex, m, out=out), stream, max(3, args.steps // 2), 2, torch)
+        ms = float(np.mean(per))
+        overhead[name] = {"ms": ms, "us_per_mpixel": ms * 1e3 / (npx / 1e6)}
+    ctex.close()
     b4 = res["bilinear4"]["gpixels_per_s"]
     # ALU roofline of the texel evaluations: per term 7 full-rate VALU
     # instructions (2 mul24, add3, and, cvt, mul, fma) and one v_sin_f32 at
@@ -221,7 +232,8 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
     tex.close()
     return {"workload": "1920x1080 four-plane frame, 2048^2 procedural texture (K=32 sinusoids "
                         "per channel, F=64), per-lane texel production; *_8x4: the paper's 8x4 tiles, "
-                        "two per wave64", "roofline": roof, "methods": res}
+                        "two per wave64", "roofline": roof, "methods": res,
+            "constant_texture_overhead": overhead}
 
 
 def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):

@@ -265,3 +265,20 @@ def test_launch_configuration_procedural_1080p_sampled(G, c1080, name, gk, ok, b
     check_tile_rows(g["out"], g["stf"],
                     lambda tr: O.filter(sc.uv, sc.duv, otex, om, seed=0, tiles=tr, stf=True, tile=(8, th)),
                     sampled_tile_rows(1080 // th, 6, 11), 240, th, TOL, name)
+
+
+@pytest.mark.parametrize("name,gk,ok,box", [("bilinear4", 0, O.BILINEAR4, (0, 0)), ("stf1", 1, O.STF1, (0, 0)),
+                                            ("list", 2, O.LIST, (0, 0)), ("box6x6", 3, O.BOX, (6, 6)),
+                                            ("mask", 4, O.MASK, (0, 0))])
+def test_launch_configuration_constant_texture(G, name, gk, ok, box):
+    """The constant texture the benchmark uses to time the dedup machinery
+    alone, through the same statistics-free kernels."""
+    ctf, ctx, torch = G
+    rgba = (0.25, 0.5, 0.75, 1.0)
+    tex = ctx.constant_texture(2048, 2048, rgba)
+    otex = O.constant_texture(2048, 2048, rgba)
+    for sname, uv, duv in small_scenes():
+        g = run_launch(G, uv, duv, tex, ctf.method(gk, box=box), seed=13)
+        o = O.filter(uv, duv, otex, O.method(ok, box=box), seed=13, stf=True)
+        check_frame(g, o, gk >= 2, f"{name} {sname}")
+    tex.close()
