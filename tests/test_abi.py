@@ -83,3 +83,20 @@ def test_filter_validates_screen_sides_before_the_device():
         st = ctf.lib.ctf_filter_layers(dummy, dummy, dummy, sw, sh, 1, texs, xf, ctypes.byref(m), 0, dummy,
                                        None, None, None, None)
         assert st == 1, (sw, sh, st)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the binding with no built library beside it refuses to
+    import: nothing on the product path falls back to the CPU."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2506_17770_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2506_17770_amd", "__init__.py"), pkg / "__init__.py")
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "try:\n    import paper_2506_17770_amd\nexcept ImportError as e:\n    print('refused:', e); sys.exit(7)\n"
+            "sys.exit(0)\n")
+    r = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 7, r.stdout + r.stderr
+    assert "no CPU fallback" in r.stdout
