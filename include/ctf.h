@@ -297,7 +297,10 @@ ctf_status ctf_decoder_set_state(ctf_decoder dec, const void *host, size_t bytes
  * current parameters, computed by the training kernels in `precision`
  * (CTF_BF16 or CTF_FP16 operands, float32 accumulation).
  * xy: device int32 [n][2]; target: device float [n][4]; loss: device float
- * [1]; grad: device float [param_count] (flat layout). */
+ * [1]; grad: device float [param_count] (flat layout).
+ * The first call with a larger n than any before grows the decoder's batch
+ * buffers (a device allocation); calls on one decoder share those buffers
+ * and must not overlap. */
 ctf_status ctf_decoder_loss_grad(ctf_decoder dec, const int32_t *xy, const float *target,
                                  int32_t n, int32_t precision, float *loss, float *grad,
                                  void *stream);
@@ -305,7 +308,11 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder dec, const int32_t *xy, const float
 /* Train with Adam (beta 0.9/0.999, eps 1e-8) for `steps` steps of `batch`
  * texels drawn uniformly from the lattice by the pcg hash of (seed, step,
  * sample); targets are produced by `target` (any texel producer).
- * loss_trace: nullable device float [steps], the loss of each step. */
+ * loss_trace: nullable device float [steps], the loss of each step.
+ * Grows the batch buffers as ctf_decoder_loss_grad does; calls on one decoder
+ * must not overlap.  Errors: CTF_ERR_INVALID_ARG (steps < 0, batch <= 0,
+ * lr <= 0, a target of another size or device), CTF_ERR_UNSUPPORTED (a
+ * decoder texture as the target). */
 ctf_status ctf_decoder_train(ctf_decoder dec, ctf_texture target, int64_t steps,
                              int32_t batch, float lr, uint64_t seed, int32_t precision,
                              float *loss_trace, void *stream);
