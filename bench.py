@@ -169,6 +169,40 @@ def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed, gpu_out=None):
     return base, err
 
 
+def cpu_oracle_procedural(sc, pqj, amp, single_s=2.0):
+    """The oracle's List on the 1080p procedural frame: one thread on whole
+    tile rows for about ``single_s`` seconds, then every tile row on all host
+    threads."""
+    import oracle as O
+    otex = O.sinusoid_texture(2048, pqj, amp)
+    meth = O.method(O.LIST)
+    tiles_x, tiles_y = (sc.width + 7) // 8, (sc.height + 7) // 8
+
+    def rows(rs):
+        for r in rs:
+            O.filter(sc.uv, sc.duv, otex, meth, seed=0, tiles=(r * tiles_x, (r + 1) * tiles_x), stats=False)
+
+    t0 = time.perf_counter()
+    n1 = 0
+    while n1 < tiles_y and time.perf_counter() - t0 < single_s:
+        rows([n1])
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    threads = os.cpu_count() or 1
+    parts = [list(range(tiles_y))[i::threads] for i in range(threads)]
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=rows, args=(p,)) for p in parts if p]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    dtn = time.perf_counter() - t0
+    return {"method": "list", "single_thread_mpixels_per_s": n1 * tiles_x * 64 / dt1 / 1e6,
+            "threads": len(ths), "mpixels_per_s": tiles_y * tiles_x * 64 / dtn / 1e6,
+            "sample": f"one thread: {n1} of {tiles_y} tile rows ({dt1:.1f} s); {len(ths)} threads: all "
+                      f"{tiles_y} tile rows ({dtn:.1f} s); float64 texels"}
+
+
 def bench_procedural(ctx, ctf, cs, torch, args, stream):
     """1920x1080 four-plane frame, 2048^2 procedural texture (32 sinusoids per
     channel): every method through the per-lane kernel."""
@@ -214,6 +248,7 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
         ms = float(np.mean(per))
         overhead[name] = {"ms": ms, "us_per_mpixel": ms * 1e3 / (npx / 1e6)}
     ctex.close()
+    cpu = None if args.no_cpu_baseline else cpu_oracle_procedural(sc, pqj, amp)
     b4 = res["bilinear4"]["gpixels_per_s"]
     # ALU roofline of the texel evaluations: per term 7 full-rate VALU
     # instructions (2 mul24, add3, and, cvt, mul, fma) and one v_sin_f32 at
@@ -233,7 +268,7 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
     return {"workload": "1920x1080 four-plane frame, 2048^2 procedural texture (K=32 sinusoids "
                         "per channel, F=64), per-lane texel production; *_8x4: the paper's 8x4 tiles, "
                         "two per wave64", "roofline": roof, "methods": res,
-            "constant_texture_overhead": overhead}
+            "constant_texture_overhead": overhead, "cpu_oracle": cpu}
 
 
 def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
