@@ -87,10 +87,12 @@ enum { CTF_FILTER_BILINEAR = 0, CTF_FILTER_BSPLINE = 1, CTF_FILTER_CATMULL_ROM =
 
 /* Split-texel production (the idea of Section 5's DCT discussion: spread one
  * texel's work over idle lanes).  With CTF_SPLIT_AUTO, a procedural-texture
- * wave whose collaborative step succeeded with no one-tap draws and n <= 32
- * (n <= 16) texels evaluates each texel on 2 (4) lanes, one channel pair
- * (one channel) per lane, reading the terms from LDS (textures of at most
- * 64 terms per channel).  Results are bit-identical either way. */
+ * wave whose collaborative step succeeded with no one-tap draws spreads the
+ * 4n channels of its n texels over all 64 lanes (item j / 4, channel j % 4
+ * for j = lane, lane + 64, ...) whenever that takes fewer channel
+ * evaluations per lane, ceil(n / 16), than one texel per lane of A,
+ * 4 ceil(n / |A|); the terms are read from LDS (textures of at most 64 terms
+ * per channel).  Results are bit-identical either way. */
 enum { CTF_SPLIT_AUTO = 0, CTF_SPLIT_OFF = 1 };
 
 /* Wave shape.  CTF_WAVE_8X8: one 8x8-pixel tile per wave64 (lane = 8 ly + lx).

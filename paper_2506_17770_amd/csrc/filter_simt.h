@@ -302,23 +302,23 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
             auto list_out = [&](int item, int2 e) {
                 if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = e;
             };
-            // split-texel production: a wave with n <= 32 (16) texels and no
-            // one-tap draws evaluates each texel on 2 (4) lanes, one channel
-            // pair (one channel) per lane, over all 64 lanes
+            // split-texel production: a successful wave with no one-tap
+            // draws evaluates its 4n texel channels over all 64 lanes (lane l
+            // takes channels l, l + 64, ...: item j / 4, channel j % 4), when
+            // that takes fewer channel evaluations per lane, ceil(n / 16), than
+            // one texel per lane of A, 4 ceil(n / |A|)
             bool split = false;
             if constexpr (kCanSplit) {
-                split = split_ok && success && stfmask == 0 && n <= 32;
+                split = split_ok && success && stfmask == 0 && (n + 15) / 16 < 4 * ((n + nA - 1) / nA);
                 if (split) {
-                    const int ls = n <= 16 ? 2 : 1;    // log2 of lanes per texel
-                    const int item = lane >> ls, part = lane & ((1 << ls) - 1);
-                    if (item < n) {
+                    const int K = T.n_terms;
+                    for (int j = lane; j < 4 * n; j += kWave) {
+                        const int item = j >> 2, c = j & 3;
                         const int2 e = item_xy(item);
-                        if (part == 0) list_out(item, e);
+                        if (c == 0) list_out(item, e);
                         float* v = reinterpret_cast<float*>(&L.vals[item]);
-                        const int K = T.n_terms, nc = 4 >> ls, c0 = part * nc;
-                        const int xm = e.x & (int)T.wmask, ym = e.y & (int)T.wmask;
-                        v[c0] = sinusoid_channel(terms_lds + c0 * K, K, T.wmask, T.inv_w, xm, ym);
-                        if (nc == 2) v[c0 + 1] = sinusoid_channel(terms_lds + (c0 + 1) * K, K, T.wmask, T.inv_w, xm, ym);
+                        v[c] = sinusoid_channel(terms_lds + c * K, K, T.wmask, T.inv_w, e.x & (int)T.wmask,
+                                                e.y & (int)T.wmask);
                     }
                 }
             }

@@ -271,20 +271,38 @@ def test_1080p_four_planes_sampled_parity(G, c1, name, gk, ok, box, k):
     tex.close()
 
 
+def _split_rule(st):
+    """Tiles the library evaluates channel by channel over all 64 lanes:
+    successful, no draws, ceil(n / 16) < 4 ceil(n / |A|)."""
+    nA = np.array([bin(int(x)).count("1") for x in st["part"]], np.int64)
+    n = st["n"].astype(np.int64)
+    ok = ((st["flags"] & O.TILE_OK) != 0) & (st["stf"] == 0) & (nA > 0)
+    per_lane = 4 * ((n + np.maximum(nA, 1) - 1) // np.maximum(nA, 1))
+    return ok & ((n + 15) // 16 < per_lane), n
+
+
 @pytest.mark.parametrize("name,gk,ok,box,k", [m for m in METHODS if m[1] >= 2])
 def test_split_texel_production_is_bitwise_identical(G, c0, name, gk, ok, box, k):
-    """Split-texel production (2 or 4 lanes per texel on small sets) gives
-    the same bits, lists and counts as one lane per texel."""
+    """Split-texel production (the 4n channels of a wave's texels spread
+    over all 64 lanes) gives the same bits, lists and counts as one lane per
+    texel: on the tilted plane (mostly n <= 32) and on head-on quads from
+    0.45x (n up to 4 |A|)."""
     ctf, ctx, _ = G
     sc, pqj, amp = c0
     tex = ctx.sinusoid_texture(64, pqj, amp)
-    on = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_AUTO), seed=4)
-    off = run_gpu(G, sc.uv, sc.duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_OFF), seed=4)
-    st = on["stats"]
-    split_tiles = ((st["flags"] & O.TILE_OK) != 0) & (st["stf"] == 0) & (st["n"] <= 32)
-    assert split_tiles.sum() > 20
-    assert np.array_equal(on["out"], off["out"])
-    assert np.array_equal(on["lists"], off["lists"])
-    for f in STAT_FIELDS:
-        assert np.array_equal(on["stats"][f], off["stats"][f]), f
+    quads = cs.lowmag_quads_scene(300, seed=5, tex_w=64, mag=(0.45, 4.0))
+    total, wide = 0, 0
+    for uv, duv in ((sc.uv, sc.duv), quads):
+        on = run_gpu(G, uv, duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_AUTO), seed=4)
+        off = run_gpu(G, uv, duv, tex, ctf.method(gk, box=box, k=k, split=ctf.SPLIT_OFF), seed=4)
+        split_tiles, n = _split_rule(on["stats"])
+        total += int(split_tiles.sum())
+        wide += int((split_tiles & (n > 32)).sum())
+        assert np.array_equal(on["out"], off["out"])
+        assert np.array_equal(on["lists"], off["lists"])
+        for f in STAT_FIELDS:
+            assert np.array_equal(on["stats"][f], off["stats"][f]), f
+    assert total > 20
+    if box != (4, 4):
+        assert wide > 0, "no split wave with more than 32 texels"
     tex.close()
