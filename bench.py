@@ -61,7 +61,7 @@ def parse():
 KERNEL_SOURCES = ["paper_2506_17770_amd/csrc/filter_decoder.hip", "paper_2506_17770_amd/csrc/filter_decoder.h",
                   "paper_2506_17770_amd/csrc/decoder_mlp.h",
                   "paper_2506_17770_amd/csrc/ctf_device.h", "paper_2506_17770_amd/csrc/ctf_internal.h",
-                  "paper_2506_17770_amd/csrc/fallback.h"]
+                  "paper_2506_17770_amd/csrc/fallback.h", "paper_2506_17770_amd/build.py"]
 TRAFFIC_RECORD = "profiles/k_filter_dec_list_fp16_4k.json"
 
 

@@ -27,6 +27,13 @@ HIPCC_FLAGS = [
 ]
 NOISE = "is not a recognized feature for this target"
 
+# Per-source code generation: the decoder filter kernels are scheduled for
+# instruction-level parallelism (their occupancy is fixed by the launch
+# bounds); measured on the 4K List frame: 203-205 us against 216-217 us.
+SOURCE_FLAGS = {
+    "filter_decoder.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
 
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
@@ -46,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(objdir, exist_ok=True)
     srcs = sources()
     objs = [os.path.join(objdir, os.path.basename(f) + ".o") for f in srcs]
-    cmds = [[hipcc] + HIPCC_FLAGS + ["-c", f, "-o", o] for f, o in zip(srcs, objs)]
+    cmds = [[hipcc] + HIPCC_FLAGS + SOURCE_FLAGS.get(os.path.basename(f), []) + ["-c", f, "-o", o]
+            for f, o in zip(srcs, objs)]
     jobs = jobs or min(len(cmds), os.cpu_count() or 1, 16)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_run, cmds))

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
     constexpr bool kCanSplit = (METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK) &&
                                TEX == CTF_TEX_SINUSOIDS;
     __shared__ WaveLds<F> lds_all[kWavesPerBlock];
-    __shared__ int4 terms_lds[kCanSplit ? 4 * kSplitTerms : 1];
+    // the four channels' terms, each channel's row padded by one entry so
+    // that the lanes of a split round, which read the same term of
+    // different channels, hit different LDS banks
+    __shared__ int4 terms_lds[kCanSplit ? 4 * (kSplitTerms + 1) : 1];
     const int wid = wave_in_block();
     const int lane = lane_id();
     WaveLds<F>& L = lds_all[wid];
@@ -119,7 +122,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
     if constexpr (kCanSplit) {
         split_ok = a.split == CTF_SPLIT_AUTO && T.n_terms <= kSplitTerms;
         if (split_ok) {
-            for (int i = threadIdx.x; i < 4 * T.n_terms; i += blockDim.x) terms_lds[i] = T.terms[i];
+            for (int i = threadIdx.x; i < 4 * T.n_terms; i += blockDim.x)
+                terms_lds[i + i / T.n_terms] = T.terms[i];
             __syncthreads();
         }
     }
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                         const int2 e = item_xy(item);
                         if (c == 0) list_out(item, e);
                         float* v = reinterpret_cast<float*>(&L.vals[item]);
-                        v[c] = sinusoid_channel(terms_lds + c * K, K, T.wmask, T.inv_w, e.x & (int)T.wmask,
+                        v[c] = sinusoid_channel(terms_lds + c * (K + 1), K, T.wmask, T.inv_w, e.x & (int)T.wmask,
                                                 e.y & (int)T.wmask);
                     }
                 }
