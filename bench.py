@@ -61,8 +61,21 @@ def parse():
 KERNEL_SOURCES = ["paper_2506_17770_amd/csrc/filter_decoder.hip", "paper_2506_17770_amd/csrc/filter_decoder.h",
                   "paper_2506_17770_amd/csrc/decoder_mlp.h",
                   "paper_2506_17770_amd/csrc/ctf_device.h", "paper_2506_17770_amd/csrc/ctf_internal.h",
-                  "paper_2506_17770_amd/csrc/fallback.h", "paper_2506_17770_amd/build.py"]
+                  "paper_2506_17770_amd/csrc/fallback.h"]
+KERNEL_OBJECT = "filter_decoder.hip"   # the source the List kernel is compiled from
 TRAFFIC_RECORD = "profiles/k_filter_dec_list_fp16_4k.json"
+
+
+def kernel_compile_flags():
+    """The hipcc flags the List kernel's source is compiled with (include
+    paths left out: they name the checkout's location)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("ctf_hip_build_flags",
+                                                  os.path.join(ROOT, "paper_2506_17770_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    flags = mod.HIPCC_FLAGS + mod.SOURCE_FLAGS.get(KERNEL_OBJECT, [])
+    return [f for f in flags if not f.startswith("-I")]
 
 
 def kernel_source_digest() -> str:
@@ -70,6 +83,7 @@ def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
+    h.update(" ".join(kernel_compile_flags()).encode())
     return h.hexdigest()
 
 
