@@ -26,6 +26,7 @@ FILTER_BILINEAR, FILTER_BSPLINE, FILTER_CATMULL_ROM = 0, 1, 2
 TEX_SINUSOIDS, TEX_AFFINE, TEX_CONSTANT, TEX_TABLE, TEX_DECODER = 0, 1, 2, 3, 4
 TILE_OK, TILE_CAP, TILE_OVERFLOW, TILE_EMPTY = 1, 2, 4, 8
 MAX_ITEMS = 256
+MAX_FB_ITEMS = 128
 
 
 def build() -> str:
@@ -88,7 +89,7 @@ def lib():
         L.ctfo_filter.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.POINTER(Texture),
                                   ctypes.POINTER(Method), ctypes.c_uint64, ctypes.c_int32,
-                                  P, P, P, P, P, ctypes.c_int64, ctypes.c_int64]
+                                  P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int64]
         L.ctfo_cplus_target.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ctfo_decoder_loss_grad.argtypes = [ctypes.POINTER(Decoder), P, P, ctypes.c_int64,
                                              P, P]
@@ -208,12 +209,14 @@ def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_
 
 
 def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 8),
-           tiles=None, stats=True, lists=False, stf=False, xform=None):
-    """Run the oracle filter.  Returns dict(out f64 [H][W][4], stats, lists, stf).
+           tiles=None, stats=True, lists=False, stf=False, xform=None, fb_items=False):
+    """Run the oracle filter.  Returns dict(out f64 [H][W][4], stats, lists, stf, fb_items).
 
     ``tiles`` = (begin, end) restricts the work to a tile range (the other
     pixels of ``out`` are left zero).  ``xform`` = 2x2 matrix of a material
-    layer applied (in float32) to uv and its derivatives.
+    layer applied (in float32) to uv and its derivatives.  ``fb_items``:
+    return, per tile, the texels fallback C or C+ produced as rows
+    (x, y, rank in A of the producing lane), padded with INT32_MIN.
     """
     xf = None if xform is None else np.ascontiguousarray(np.asarray(xform, np.float32).reshape(4))
     uv = np.ascontiguousarray(uv, dtype=np.float32)
@@ -225,13 +228,14 @@ def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 
     st = np.zeros(ntiles, TILE_STATS_DTYPE) if stats else None
     li = np.full((ntiles, MAX_ITEMS, 2), np.iinfo(np.int32).min, np.int32) if lists else None
     sx = np.full((sh, sw, 2), np.iinfo(np.int32).min, np.int32) if stf else None
+    fi = np.full((ntiles, MAX_FB_ITEMS, 3), np.iinfo(np.int32).min, np.int32) if fb_items else None
     b, e = tiles if tiles is not None else (0, ntiles)
     rc = lib().ctfo_filter(_ptr(uv), _ptr(duv), sw, sh, tw, th, ctypes.byref(tex.struct),
                            ctypes.byref(meth), seed & (2**64 - 1), layer, _ptr(xf), _ptr(out), _ptr(st),
-                           _ptr(li), _ptr(sx), b, e)
+                           _ptr(li), _ptr(sx), _ptr(fi), b, e)
     if rc:
         raise RuntimeError(f"ctfo_filter failed ({rc})")
-    return dict(out=out, stats=st, lists=li, stf=sx)
+    return dict(out=out, stats=st, lists=li, stf=sx, fb_items=fi)
 
 
 def decoder_loss_grad(params, xy, target, l0, l1, hidden, tex_w, channels=8, grad=True):

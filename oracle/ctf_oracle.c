@@ -358,7 +358,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 const ctfo_texture *tex, const ctfo_method *m,
                 uint64_t seed, int32_t layer, const float *xform,
                 double *out, ctfo_tile_stats *stats, int32_t *lists, int32_t *stf_xy,
-                int64_t tile_begin, int64_t tile_end)
+                int32_t *fb_items, int64_t tile_begin, int64_t tile_end)
 {
     if (!uv || !duv || !tex || !m || !out) return 1;
     if (sw <= 0 || sh <= 0 || tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > MAX_LANES) return 1;
@@ -495,6 +495,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
             fb = m->fallback;
         if (fb == CTFO_FB_CPLUS && !fits16) fb = CTFO_FB_C;
         texel_t prod[2 * MAX_LANES];
+        int prod_rank[2 * MAX_LANES];   /* rank in A of the lane producing prod[i] */
         int nprod = 0, fb_evals = 0;
         if (fb == CTFO_FB_C) {
             for (int l = 0; l < nl; ++l) {
@@ -503,6 +504,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 stf_pick(&lanes[l], seed, layer, pk);
                 prod[nprod].x = pk[0];
                 prod[nprod].y = pk[1];
+                prod_rank[nprod] = nprod;
                 ++nprod;
             }
             fb_evals = nA;
@@ -523,6 +525,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 int t = ctfo_bit_select(Sm, i);
                 prod[nprod].x = (int32_t)(xmin + (t & 15));
                 prod[nprod].y = (int32_t)(ymin + (t >> 4));
+                prod_rank[nprod] = i;
                 ++nprod;
             }
             fb_evals = ns;
@@ -556,6 +559,7 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 }
                 prod[nprod].x = T->ox + pickq % F;
                 prod[nprod].y = T->oy + pickq / F;
+                prod_rank[nprod] = c;
                 ++nprod;
                 ++fb_evals;
             }
@@ -626,6 +630,13 @@ int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
         }
         if (success) evals += n;
 
+        if (fb_items && fb != CTFO_FB_STF1)
+            for (int i = 0; i < nprod; ++i) {
+                int32_t *e = fb_items + (tile * CTFO_MAX_FB_ITEMS + i) * 3;
+                e[0] = prod[i].x;
+                e[1] = prod[i].y;
+                e[2] = prod_rank[i];
+            }
         if (lists && success)
             for (int64_t i = 0; i < n; ++i) {
                 lists[(tile * MAX_ITEMS + i) * 2] = items[i].x;

@@ -86,13 +86,18 @@ int ctfo_cplus_target(int32_t nA, int32_t ns, int32_t c);   /* Eq. 2 */
 
 /* xform: nullable 2x2 row-major matrix M applied to uv and to each
  * derivative pair before the footprint (a material layer's texture
- * coordinates), in float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u). */
+ * coordinates), in float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u).
+ * fb_items: nullable [tiles][CTFO_MAX_FB_ITEMS][3]; for a tile that takes
+ * fallback C or C+ it receives the texels the fallback produced, in the
+ * order they are produced, as (x, y, rank in A of the producing lane);
+ * unused entries (and tiles without such a fallback) are left untouched. */
+#define CTFO_MAX_FB_ITEMS 128
 int ctfo_filter(const float *uv, const float *duv, int32_t sw, int32_t sh,
                 int32_t tile_w, int32_t tile_h,
                 const ctfo_texture *tex, const ctfo_method *m,
                 uint64_t seed, int32_t layer, const float *xform,
                 double *out, ctfo_tile_stats *stats, int32_t *lists, int32_t *stf_xy,
-                int64_t tile_begin, int64_t tile_end);
+                int32_t *fb_items, int64_t tile_begin, int64_t tile_end);
 
 int ctfo_decoder_loss_grad(const ctfo_decoder *dec, const int32_t *xy, const float *target,
                            int64_t n, double *loss, double *grad);

@@ -500,3 +500,283 @@ def test_fallback_quality_order():
             errs.append(((o - ex) ** 2).mean())
         mse[name] = np.mean(errs)
     assert mse["cplus"] < mse["c"] < mse["stf"], mse
+
+
+# ---------------------------------------------------------------------------
+# decoder: where the ReLUs sit (hidden pre-activations of both signs)
+# ---------------------------------------------------------------------------
+
+def _signed_network(tex_w=32, l0=8, l1=4, C=8, seed=12):
+    """A hand-built decoder whose hidden units split each feature f into its
+    positive and negative parts.
+
+    Layer 1 (2C -> H = 4C): unit i = f_i, unit 2C + i = -f_i (W1 = [I, -I],
+    no bias), so its ReLU yields (max(f, 0), max(-f, 0)).  Layer 2: unit
+    j = a_j - a_{2C+j} + beta_p, unit 2C + j = -(a_j - a_{2C+j}) + beta_n,
+    i.e. f_j + beta_p and -f_j + beta_n before its ReLU.  Output c:
+    1 x unit c + 2 x unit 2C + c + 3 x unit C + c + 4 x unit 3C + c of the
+    second layer's activations, plus b3_c.  Latents are drawn from U(-1, 1),
+    so every pre-activation takes both signs.
+    """
+    H = 4 * C
+    lay = cs.decoder_layout(l0, l1, H, C)
+    rng = np.random.default_rng(seed)
+    p = np.zeros(lay["total"][1])
+    o, n = lay["lat0"]; p[o:o + n] = rng.uniform(-1, 1, n)
+    o, n = lay["lat1"]; p[o:o + n] = rng.uniform(-1, 1, n)
+    F = 2 * C
+    W1 = np.zeros((F, H))
+    W1[np.arange(F), np.arange(F)] = 1
+    W1[np.arange(F), F + np.arange(F)] = -1
+    W2 = np.zeros((H, H))
+    for j in range(F):
+        W2[j, j], W2[F + j, j] = 1, -1
+        W2[j, F + j], W2[F + j, F + j] = -1, 1
+    beta_p, beta_n = 0.125, -0.25
+    b2 = np.concatenate([np.full(F, beta_p), np.full(F, beta_n)])
+    W3 = np.zeros((H, 4))
+    for c in range(4):
+        W3[c, c], W3[F + c, c] = 1, 2              # level 0, channel c
+        W3[C + c, c], W3[F + C + c, c] = 3, 4      # level 1, channel c
+    b3 = np.array([-1.0, -0.5, 0.25, -2.0])
+    for name, v in (("W1", W1), ("W2", W2), ("b2", b2), ("W3", W3), ("b3", b3)):
+        o, n = lay[name]
+        p[o:o + n] = v.ravel()
+    return dict(p=p, lay=lay, tex_w=tex_w, l0=l0, l1=l1, H=H, C=C,
+                beta_p=beta_p, beta_n=beta_n, b3=b3)
+
+
+def _bilinear_corners(xy, L, tex_w):
+    """Corner cells and weights of the repeat-addressed bilinear sample at
+    g = (x + 1/2) L / W - 1/2, per sample: ([n][4] flat cell index, [n][4] weight)."""
+    g = (xy.astype(np.float64) + 0.5) * L / tex_w - 0.5
+    c = np.floor(g)
+    f = g - c
+    cx, cy = c[:, 0].astype(np.int64), c[:, 1].astype(np.int64)
+    fx, fy = f[:, 0], f[:, 1]
+    idx = np.stack([(cy % L) * L + cx % L, (cy % L) * L + (cx + 1) % L,
+                    ((cy + 1) % L) * L + cx % L, ((cy + 1) % L) * L + (cx + 1) % L], 1)
+    w = np.stack([(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy], 1)
+    return idx, w
+
+
+def _signed_features(net, xy):
+    """Level-0 and level-1 features by scipy's map_coordinates (order 1, grid-wrap)."""
+    from scipy.ndimage import map_coordinates
+    lay, C = net["lay"], net["C"]
+    feats = []
+    for name, L in (("lat0", net["l0"]), ("lat1", net["l1"])):
+        o, n = lay[name]
+        grid = net["p"][o:o + n].reshape(L, L, C)
+        gx = (xy[:, 0] + 0.5) * L / net["tex_w"] - 0.5
+        gy = (xy[:, 1] + 0.5) * L / net["tex_w"] - 0.5
+        feats.append(np.stack([map_coordinates(grid[..., c], [gy, gx], order=1, mode="grid-wrap")
+                               for c in range(C)], 1))
+    return feats
+
+
+def test_decoder_relu_placement_closed_form():
+    """Forward pass of the signed network against its closed form:
+    out_c = max(f0+bp, 0) + 2 max(-f0+bn, 0) + 3 max(f1+bp, 0) + 4 max(-f1+bn, 0) + b3_c
+    with f0, f1 the level-0 and level-1 features of channel c.  A missing,
+    extra (output) or moved ReLU changes the result."""
+    net = _signed_network()
+    tex = O.decoder_texture(net["tex_w"], net["l0"], net["l1"], net["H"], net["p"])
+    rng = np.random.default_rng(4)
+    xy = rng.integers(-50, 90, (400, 2)).astype(np.int32)
+    got = tex.eval(xy)
+    f0, f1 = _signed_features(net, xy)
+    bp, bn = net["beta_p"], net["beta_n"]
+    relu = lambda v: np.maximum(v, 0.0)
+    want = np.stack([relu(f0[:, c] + bp) + 2 * relu(-f0[:, c] + bn)
+                     + 3 * relu(f1[:, c] + bp) + 4 * relu(-f1[:, c] + bn) + net["b3"][c]
+                     for c in range(4)], 1)
+    # both signs and both inactive bands are exercised, and outputs go negative
+    for f in (f0[:, :4], f1[:, :4]):
+        assert (f > -bp).mean() > 0.2 and (f < bn).mean() > 0.2
+        assert ((f < -bp) & (f > bn)).any()
+    assert (want < 0).mean() > 0.1
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_decoder_relu_gradients_closed_form():
+    """Backward pass of the signed network against its closed form.
+
+    With e = y - target and dy = 2 e / (4 n): dL/db3 = sum dy; dL/dW3 rows
+    are the second layer's activations times dy; dL/db2_j = sum dy_c times
+    the coefficient of unit j (1, 2, 3, 4) where that unit is active; the
+    latent gradient of channel c < 4 is dy_c times phi'(f) times the
+    corner weight, phi'(f) = [f > -bp] - 2 [f < bn] (level 0) and
+    3 [f > -bp] - 4 [f < bn] (level 1); channels 4..7 feed no output and get
+    no gradient."""
+    net = _signed_network()
+    lay, C, H = net["lay"], net["C"], net["H"]
+    rng = np.random.default_rng(6)
+    n = 300
+    xy = rng.integers(0, net["tex_w"], (n, 2)).astype(np.int32)
+    target = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    loss, g = O.decoder_loss_grad(net["p"], xy, target, net["l0"], net["l1"], H, net["tex_w"])
+    f0, f1 = _signed_features(net, xy)
+    bp, bn = net["beta_p"], net["beta_n"]
+    relu = lambda v: np.maximum(v, 0.0)
+    F = 2 * C
+    f = np.concatenate([f0, f1], 1)                       # [n][2C]
+    a2 = np.concatenate([relu(f + bp), relu(-f + bn)], 1)  # [n][H]
+    y = np.stack([a2[:, c] + 2 * a2[:, F + c] + 3 * a2[:, C + c] + 4 * a2[:, F + C + c]
+                  + net["b3"][c] for c in range(4)], 1)
+    e = y - target.astype(np.float64)
+    assert loss == pytest.approx((e ** 2).mean(), rel=1e-12)
+    dy = 2 * e / (4 * n)
+
+    o, m = lay["b3"]
+    np.testing.assert_allclose(g[o:o + m], dy.sum(0), atol=1e-12)
+    o, m = lay["W3"]
+    np.testing.assert_allclose(g[o:o + m].reshape(H, 4), a2.T @ dy, atol=1e-12)
+    coef = np.zeros((H, 4))
+    for c in range(4):
+        coef[c, c], coef[F + c, c], coef[C + c, c], coef[F + C + c, c] = 1, 2, 3, 4
+    active2 = np.concatenate([f + bp > 0, -f + bn > 0], 1)
+    o, m = lay["b2"]
+    np.testing.assert_allclose(g[o:o + m], (active2 * (dy @ coef.T)).sum(0), atol=1e-12)
+    for lev, (name, L, fl, kp, kn) in enumerate((("lat0", net["l0"], f0, 1, 2),
+                                                 ("lat1", net["l1"], f1, 3, 4))):
+        idx, w = _bilinear_corners(xy, L, net["tex_w"])
+        dphi = kp * (fl[:, :4] > -bp) - kn * (fl[:, :4] < bn)     # [n][4 channels]
+        want = np.zeros((L * L, C))
+        for q in range(4):
+            np.add.at(want[:, :4], idx[:, q], (w[:, q:q + 1] * dy * dphi))
+        o, m = lay[name]
+        np.testing.assert_allclose(g[o:o + m].reshape(L * L, C), want, atol=1e-12)
+        assert np.abs(want).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# fallback C+ (Section 3.4, Eq. 2): what each spare lane produces
+# ---------------------------------------------------------------------------
+
+def _f32_footprints(uv, W):
+    """Bilinear footprint per pixel in float32 (W a power of two, so the
+    fused multiply-add of the footprint equals the rounded product and sum):
+    (x0, y0, s, t)."""
+    uv = uv.astype(np.float32)
+    fx = uv[..., 0] * np.float32(W) - np.float32(0.5)
+    fy = uv[..., 1] * np.float32(W) - np.float32(0.5)
+    x0, y0 = np.floor(fx), np.floor(fy)
+    return x0.astype(np.int64), y0.astype(np.int64), (fx - x0).astype(np.float32), (fy - y0).astype(np.float32)
+
+
+def _cplus_waves(seed):
+    uv, duv = _lowmag_scene()
+    W = 64
+    pqj, amp = cs.sinusoid_params(W, 8, 8, seed=7)
+    tex = O.sinusoid_texture(W, pqj, amp)
+    r = O.filter(uv, duv, tex, O.method(O.MASK, fallback=O.FB_CPLUS), seed=seed, stf=True,
+                 fb_items=True)
+    return uv, W, r
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_cplus_spare_lanes_follow_eq2(seed):
+    """Per failed wave, independently of the oracle's own steps:
+    the first |S| produced texels are the distinct one-tap draws of A in
+    mask (row-major) order, made by the lanes of rank 0..|S|-1; every other
+    produced texel is made by a spare lane of rank c >= |S| and lies in the
+    footprint of the lane of rank round((nA-1)(c-|S|)/(nA-1-|S|)) (Eq. 2,
+    exact rationals, ties up), with a nonzero float32 weight there, outside
+    S; a spare lane produces nothing only when that footprint has no such
+    texel; the tile's evaluation count is |S| + the spare texels + the draws
+    of the minifying lanes."""
+    from fractions import Fraction
+    uv, W, r = _cplus_waves(seed)
+    x0, y0, s, t = _f32_footprints(uv, W)
+    n_tiles = uv.shape[1] // 8
+    checked = spare_total = idle_total = 0
+    for tile in range(n_tiles):
+        S_rec = r["stats"][tile]
+        if S_rec["flags"] & O.TILE_OK or S_rec["part"] == 0:
+            continue
+        assert S_rec["bbw"] <= 16 and S_rec["bbh"] <= 16
+        A = int(S_rec["part"])
+        lanes = [l for l in range(64) if (A >> l) & 1]
+        nA = len(lanes)
+        sl = np.s_[:, 8 * tile:8 * tile + 8]
+        tx0, ty0, ts, tt = (a[sl].reshape(64) for a in (x0, y0, s, t))
+        picks = r["stf"][sl].reshape(64, 2)
+        S = sorted({(int(picks[l, 1]), int(picks[l, 0])) for l in lanes})   # (y, x) order
+        ns = len(S)
+        items = r["fb_items"][tile]
+        items = items[items[:, 2] != np.iinfo(np.int32).min]
+        assert [(int(i[1]), int(i[0])) for i in items[:ns]] == S
+        assert list(items[:ns, 2]) == list(range(ns))
+        spare = items[ns:]
+        ranks = list(spare[:, 2])
+        assert ranks == sorted(set(ranks)) and all(ns <= c < nA for c in ranks)
+        Sset = set(S)
+        for c in range(ns, nA):
+            span = nA - 1 - ns
+            tr = 0 if span == 0 else int(Fraction((nA - 1) * (c - ns), span) + Fraction(1, 2))
+            L = lanes[tr]
+            wx = (np.float32(1) - ts[L], ts[L])
+            wy = (np.float32(1) - tt[L], tt[L])
+            cand = {(int(ty0[L] + j), int(tx0[L] + i)) for j in range(2) for i in range(2)
+                    if np.float32(wx[i] * wy[j]) != 0 and (int(ty0[L] + j), int(tx0[L] + i)) not in Sset}
+            row = spare[spare[:, 2] == c]
+            if row.size:
+                assert (int(row[0, 1]), int(row[0, 0])) in cand, (tile, c)
+                spare_total += 1
+            else:
+                assert not cand, (tile, c)
+                idle_total += 1
+        minify_draws = bin(int(S_rec["active"]) & ~A).count("1")
+        assert S_rec["evals"] == ns + len(spare) + minify_draws
+        checked += 1
+    assert checked > 300 and spare_total > 3000 and idle_total > 0
+
+
+def test_cplus_spare_draws_follow_abs_weights():
+    """A spare lane draws among its candidates with probability |w| / sum |w|:
+    the randomised probability-integral transform of every draw (a uniform
+    point inside the drawn candidate's interval of the cumulative |w|
+    distribution, candidates in row-major order) is uniform on [0, 1)."""
+    from fractions import Fraction
+    from scipy.stats import chisquare
+    pit = []
+    rng = np.random.default_rng(11)
+    for seed in range(4):
+        uv, W, r = _cplus_waves(seed)
+        x0, y0, s, t = _f32_footprints(uv, W)
+        for tile in range(uv.shape[1] // 8):
+            S_rec = r["stats"][tile]
+            if S_rec["flags"] & O.TILE_OK or S_rec["part"] == 0:
+                continue
+            A = int(S_rec["part"])
+            lanes = [l for l in range(64) if (A >> l) & 1]
+            nA = len(lanes)
+            sl = np.s_[:, 8 * tile:8 * tile + 8]
+            tx0, ty0, ts, tt = (a[sl].reshape(64) for a in (x0, y0, s, t))
+            picks = r["stf"][sl].reshape(64, 2)
+            Sset = {(int(picks[l, 1]), int(picks[l, 0])) for l in lanes}
+            ns = len(Sset)
+            items = r["fb_items"][tile]
+            for x, y, c in items[items[:, 2] != np.iinfo(np.int32).min][ns:]:
+                span = nA - 1 - ns
+                tr = 0 if span == 0 else int(Fraction((nA - 1) * (int(c) - ns), span) + Fraction(1, 2))
+                L = lanes[tr]
+                wx = (1.0 - float(ts[L]), float(ts[L]))
+                wy = (1.0 - float(tt[L]), float(tt[L]))
+                cw = [(int(ty0[L] + j), int(tx0[L] + i), abs(wx[i] * wy[j]))
+                      for j in range(2) for i in range(2)]
+                cw = [e for e in cw if e[2] > 0 and (e[0], e[1]) not in Sset]
+                tot = sum(e[2] for e in cw)
+                lo = 0.0
+                for yy, xx, w in cw:
+                    if (yy, xx) == (int(y), int(x)):
+                        pit.append((lo + rng.uniform() * w) / tot)
+                        break
+                    lo += w
+                else:
+                    raise AssertionError("spare texel not among the candidates")
+    pit = np.array(pit)
+    assert pit.size > 10000
+    counts = np.histogram(pit, bins=20, range=(0, 1))[0]
+    assert chisquare(counts).pvalue > 1e-4, counts
