@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-layers", action="store_true", help="skip the six-layer 4K runs")
     ap.add_argument("--no-bicubic", action="store_true", help="skip the bicubic 4K runs")
     ap.add_argument("--layers", type=int, default=6)
+    ap.add_argument("--details", default=os.path.join("gpurun_out", "bench_details.json"),
+                    help="file for the full per-method sections (the printed line carries a summary)")
     return ap.parse_args()
 
 
@@ -183,6 +185,41 @@ def cpu_baseline(args, sc, dec_params, l0, l1, H, tex_w, seed, gpu_out=None):
     return base, err
 
 
+def cpu_layer_errors(layer_tex, layer_vals, tex_w):
+    """Per-layer error of the GPU decoders against the float64 procedural
+    oracle over the whole tex_w^2 lattice: max abs and PSNR for each
+    precision.  ``layer_tex``: (pqj, amp) per layer; ``layer_vals``: per layer
+    {precision: float32 [tex_w^2][4] host array of decoded texels}."""
+    import oracle as O
+    ys, xs = np.mgrid[0:tex_w, 0:tex_w]
+    xy = np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], -1).astype(np.int32))
+    threads = os.cpu_count() or 1
+    parts = np.array_split(np.arange(xy.shape[0]), threads)
+    out = {}
+    t0 = time.perf_counter()
+    for l, ((pqj, amp), vals) in enumerate(zip(layer_tex, layer_vals)):
+        otex = O.sinusoid_texture(tex_w, pqj, amp)
+        ref = np.empty((xy.shape[0], 4), np.float64)
+
+        def work(ix):
+            ref[ix] = otex.eval(xy[ix])
+
+        ths = [threading.Thread(target=work, args=(ix,)) for ix in parts if ix.size]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        for pname, v in vals.items():
+            d = v.astype(np.float64) - ref
+            mse = float((d * d).mean())
+            out.setdefault(pname, {"max_abs": [], "psnr_db": []})
+            out[pname]["max_abs"].append(float(np.abs(d).max()))
+            out[pname]["psnr_db"].append(10 * math.log10(1.0 / mse) if mse > 0 else None)
+    out["reference"] = (f"float64 procedural oracle over all {tex_w}^2 texels of each layer, "
+                        f"{len(parts)} threads, {time.perf_counter() - t0:.1f} s")
+    return out
+
+
 def cpu_oracle_procedural(sc, pqj, amp, single_s=2.0):
     """The oracle's List on the 1080p procedural frame: one thread on whole
     tile rows for about ``single_s`` seconds, then every tile row on all host
@@ -291,6 +328,7 @@ def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
     n = args.layers
     tex_w, l0, l1, H = 2048, 512, 128, 64
     decs, psnr = [], {"fp16": [], "bf16": []}
+    layer_tex, layer_vals = [], []
     ys, xs = np.mgrid[0:tex_w, 0:tex_w]
     xy = torch.from_numpy(np.stack([xs.ravel(), ys.ravel()], -1).astype(np.int32)).cuda()
     fp_bf_max = []
@@ -310,6 +348,9 @@ def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
             psnr[pname].append(10 * math.log10(1.0 / mse))
             t.close()
         fp_bf_max.append(float((vals["fp16"] - vals["bf16"]).abs().max()))
+        layer_tex.append((pqj, amp))
+        if not args.no_cpu_baseline:
+            layer_vals.append({k: v.cpu().numpy() for k, v in vals.items()})
         del vals, pv
         target.close()
         decs.append(dec)
@@ -347,7 +388,7 @@ def bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv):
                         f"layer l: own 2048^2 procedural texture (seed 11+l) and learned decoder, "
                         "uv_l = s_l R(theta_l) uv, s_l ~ U[0.25, 4]",
             "layer_scales": scales, "psnr_db": psnr, "max_abs_fp16_vs_bf16": fp_bf_max,
-            "train_seconds_total": train_s, "runs": res}
+            "train_seconds_total": train_s, "runs": res}, (layer_tex, layer_vals, tex_w)
 
 
 def main():
@@ -489,17 +530,72 @@ def main():
                                                  bic[f"{fname}_full16"]["gpixels_per_s"])
         res["bicubic_4k"] = {"workload": "the 4K frame and fp16 decoder above with 4x4 bicubic footprints: List "
                                          "k=4 + one-tap draw by |w| vs all 16 taps decoded per pixel", "runs": bic}
+    layer_data = None
     if not args.no_procedural:
         log("bench: 1080p procedural texture")
         res["procedural_1080p"] = bench_procedural(ctx, ctf, cs, torch, args, stream)
     if not args.no_layers and args.layers > 0:
         log(f"bench: {args.layers} layers at 4K")
-        res["layers_4k"] = bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv)
+        res["layers_4k"], layer_data = bench_layers(ctx, ctf, cs, torch, args, stream, sc, uv, duv)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
         res["cpu_baseline"], res["frame_error_vs_fp64_oracle"] = cpu_baseline(
             args, sc, dec.params(), l0, l1, H, tex_w, seed_stf, gpu_out=col_out)
-    print(json.dumps(res), flush=True)
+        if layer_data is not None and layer_data[1]:
+            log("bench: layer decoders against the float64 procedural oracle")
+            res["layers_4k"]["error_vs_fp64_procedural"] = cpu_layer_errors(*layer_data)
+    print(json.dumps(summary_line(res, args.details)), flush=True)
+
+
+def summary_line(res, details_path):
+    """The printed record: the headline fields in full, each side section
+    reduced to its key figures; the full sections go to ``details_path``."""
+    line = {k: v for k, v in res.items() if k not in ("bicubic_4k", "procedural_1080p", "layers_4k")}
+    if "bicubic_4k" in res:
+        r = res["bicubic_4k"]["runs"]
+        line["bicubic_4k"] = {k: (round(v, 3) if not isinstance(v, dict) else
+                                  {"gpx": round(v["gpixels_per_s"], 2),
+                                   "evals_px": round(v["texel_evals_per_pixel"], 3)})
+                              for k, v in r.items()}
+    if "procedural_1080p" in res:
+        p = res["procedural_1080p"]
+        line["procedural_1080p"] = {
+            "roofline_frac_list": round(p["roofline"]["frac"], 4),
+            "methods": {k: {"gpx": round(v["gpixels_per_s"], 2), "x_b4": round(v["speedup_vs_bilinear4"], 2),
+                            "evals_px": round(v["texel_evals_per_pixel"], 3), "alu_frac": round(v["alu_frac"], 3)}
+                        for k, v in p["methods"].items()},
+            "overhead_us_per_mpixel": {k: round(v["us_per_mpixel"], 2)
+                                       for k, v in p["constant_texture_overhead"].items()}}
+        if p.get("cpu_oracle"):
+            line["procedural_1080p"]["cpu_oracle_mpixels_per_s"] = round(p["cpu_oracle"]["mpixels_per_s"], 3)
+    if "layers_4k" in res:
+        L = res["layers_4k"]
+        s = {"psnr_db": {k: [round(x, 2) for x in v] for k, v in L["psnr_db"].items()},
+             "max_abs_fp16_vs_bf16": [float(f"{x:.3g}") for x in L["max_abs_fp16_vs_bf16"]]}
+        for k, v in L["runs"].items():
+            s[k] = (round(v, 3) if not isinstance(v, dict) else
+                    {"layer_gpx": round(v["layer_gpixels_per_s"], 2), "ms": round(v["ms"], 4),
+                     "mfma_frac": round(v["mfma_frac"], 4)})
+        if "error_vs_fp64_procedural" in L:
+            e = L["error_vs_fp64_procedural"]
+            s["error_vs_fp64_procedural"] = {
+                k: {"max_abs": [float(f"{x:.3g}") for x in e[k]["max_abs"]],
+                    "psnr_db": [round(x, 2) for x in e[k]["psnr_db"]]} for k in ("fp16", "bf16") if k in e}
+        line["layers_4k"] = s
+    try:
+        d = os.path.dirname(details_path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(details_path, "w") as f:
+            json.dump(res, f, indent=1)
+        line["details"] = details_path
+    except OSError as e:
+        line["details"] = f"not written: {e}"
+    # the metric's ratio and the figures it rests on, last on the line
+    for k in ("texel_evals_per_pixel", "bilinear4", "speedup_vs_bilinear4", "roofline"):
+        if k in line:
+            line[k] = line.pop(k)
+    return line
 
 
 if __name__ == "__main__":
