@@ -37,6 +37,7 @@ TILE_STATS_DTYPE = np.dtype([
     ("n", "<i4"), ("unique", "<i4"), ("evals", "<i4"), ("flags", "<i4"),
     ("reserved", "<i4", (10,))])
 FRAME_STATS_FIELDS = ("evals", "active", "stf", "minify", "tiles", "tiles_ok", "tiles_fail", "rows")
+FRAME_STATS_WORDS = 16   # ctf_frame_stats: 8 counters + 8 reserved uint64
 
 
 class CtfError(RuntimeError):
@@ -120,6 +121,38 @@ def _dptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _buf(t, name: str, dtype, numel: int, device: int) -> Optional[int]:
+    """Device pointer of a caller buffer after checking what the library will
+    read or write through it: a contiguous tensor on the context's device,
+    of ``dtype`` (None: any dtype, counted in bytes), holding at least
+    ``numel`` elements (bytes when dtype is None).  None passes NULL."""
+    if t is None:
+        return None
+    if not getattr(t, "is_cuda", False):
+        raise CtfError(f"{name}: expected a tensor in GPU memory")
+    if t.device.index != device:
+        raise CtfError(f"{name}: tensor on cuda:{t.device.index}, the context is on cuda:{device}")
+    if not t.is_contiguous():
+        raise CtfError(f"{name}: expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise CtfError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    have = t.numel() if dtype is not None else t.numel() * t.element_size()
+    if have < numel:
+        unit = "elements" if dtype is not None else "bytes"
+        raise CtfError(f"{name}: {have} {unit}, the call needs {numel}")
+    return t.data_ptr()
+
+
+def tile_height(meth: Optional[Method]) -> int:
+    """Pixel rows per tile record: 4 for the paper's 8x4 waves, else 8."""
+    return 4 if meth is not None and meth.wave_shape == WAVE_8X4 else 8
+
+
+def n_tiles(sw: int, sh: int, meth: Optional[Method] = None) -> int:
+    th = tile_height(meth)
+    return ((sw + 7) // 8) * ((sh + th - 1) // th)
+
+
 def _stream(stream) -> Optional[int]:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -193,16 +226,22 @@ class Context:
     def filter(self, uv, duv, tex: "Texture", meth: Method, seed=0, out=None, tile_stats=None,
                frame_stats=None, lists=None, stf=None, stream=None):
         """ctf_filter on torch tensors; optional outputs are tensors or None."""
+        import torch
+        if uv.dim() != 3 or uv.shape[-1] != 2:
+            raise CtfError("uv must be [H][W][2]")
         sh, sw = uv.shape[:2]
-        if uv.shape[-1] != 2 or tuple(duv.shape) != (sh, sw, 4):
+        if tuple(duv.shape) != (sh, sw, 4):
             raise CtfError("uv must be [H][W][2] and duv [H][W][4]")
         if out is None:
-            import torch
             out = torch.empty((sh, sw, 4), dtype=torch.float32, device=uv.device)
-        _check(lib.ctf_filter(self.handle, _dptr(uv), _dptr(duv), sw, sh, tex.handle,
-                              ctypes.byref(meth), seed & (2**64 - 1), _dptr(out),
-                              _dptr(tile_stats), _dptr(frame_stats), _dptr(lists), _dptr(stf),
-                              _stream(stream)))
+        dev, npx, nt = self.device, sh * sw, n_tiles(sw, sh, meth)
+        f32, i32 = torch.float32, torch.int32
+        args = (_buf(uv, "uv", f32, npx * 2, dev), _buf(duv, "duv", f32, npx * 4, dev), sw, sh, tex.handle,
+                ctypes.byref(meth), seed & (2**64 - 1), _buf(out, "out", f32, npx * 4, dev),
+                _buf(tile_stats, "tile_stats", None, nt * TILE_STATS_DTYPE.itemsize, dev),
+                _buf(frame_stats, "frame_stats", torch.int64, FRAME_STATS_WORDS, dev),
+                _buf(lists, "lists", i32, nt * MAX_ITEMS * 2, dev), _buf(stf, "stf", i32, npx * 2, dev))
+        _check(lib.ctf_filter(self.handle, *args, _stream(stream)))
         return out
 
     def filter_layers(self, uv, duv, texs, xforms, meth: Method, seed=0, out=None, tile_stats=None,
@@ -210,17 +249,25 @@ class Context:
         """ctf_filter_layers: one launch over len(texs) material layers.
 
         xforms: [L][2][2] (layer uv = M uv); out: [L][H][W][4]."""
+        import torch
+        if uv.dim() != 3 or uv.shape[-1] != 2:
+            raise CtfError("uv must be [H][W][2]")
         sh, sw = uv.shape[:2]
+        if tuple(duv.shape) != (sh, sw, 4):
+            raise CtfError("uv must be [H][W][2] and duv [H][W][4]")
         n = len(texs)
         xf = np.ascontiguousarray(np.asarray(xforms, dtype=np.float32).reshape(n, 4))
         handles = (ctypes.c_void_p * n)(*[t.handle.value for t in texs])
         if out is None:
-            import torch
             out = torch.empty((n, sh, sw, 4), dtype=torch.float32, device=uv.device)
-        _check(lib.ctf_filter_layers(self.handle, _dptr(uv), _dptr(duv), sw, sh, n, handles,
-                                     xf.ctypes.data, ctypes.byref(meth), seed & (2**64 - 1),
-                                     _dptr(out), _dptr(tile_stats), _dptr(frame_stats), _dptr(stf),
-                                     _stream(stream)))
+        dev, npx, nt = self.device, sh * sw, n_tiles(sw, sh, meth)
+        f32, i32 = torch.float32, torch.int32
+        args = (_buf(uv, "uv", f32, npx * 2, dev), _buf(duv, "duv", f32, npx * 4, dev), sw, sh, n, handles,
+                xf.ctypes.data, ctypes.byref(meth), seed & (2**64 - 1), _buf(out, "out", f32, n * npx * 4, dev),
+                _buf(tile_stats, "tile_stats", None, n * nt * TILE_STATS_DTYPE.itemsize, dev),
+                _buf(frame_stats, "frame_stats", torch.int64, FRAME_STATS_WORDS, dev),
+                _buf(stf, "stf", i32, n * npx * 2, dev))
+        _check(lib.ctf_filter_layers(self.handle, *args, _stream(stream)))
         return out
 
     def decoder(self, l0, l1, hidden, tex_w, init, channels=8) -> "Decoder":
@@ -234,10 +281,14 @@ class Texture:
     def eval(self, xy, out=None, stream=None):
         """Texel values rgba[i] = f(xy[i]); xy int32 [n][2] on the GPU."""
         import torch
+        if xy.dim() != 2 or xy.shape[1] != 2:
+            raise CtfError("xy must be [n][2]")
         n = xy.shape[0]
         if out is None:
             out = torch.empty((n, 4), dtype=torch.float32, device=xy.device)
-        _check(lib.ctf_texture_eval(self.handle, _dptr(xy), n, _dptr(out), _stream(stream)))
+        dev = self.ctx.device
+        _check(lib.ctf_texture_eval(self.handle, _buf(xy, "xy", torch.int32, n * 2, dev), n,
+                                    _buf(out, "out", torch.float32, n * 4, dev), _stream(stream)))
         return out
 
     def close(self):
@@ -282,17 +333,22 @@ class Decoder:
 
     def loss_grad(self, xy, target, precision=BF16, stream=None):
         import torch
+        if xy.dim() != 2 or xy.shape[1] != 2:
+            raise CtfError("xy must be [n][2]")
+        n, dev = xy.shape[0], self.ctx.device
         loss = torch.zeros(1, dtype=torch.float32, device=xy.device)
         grad = torch.zeros(self.count, dtype=torch.float32, device=xy.device)
-        _check(lib.ctf_decoder_loss_grad(self.handle, _dptr(xy), _dptr(target), xy.shape[0],
+        _check(lib.ctf_decoder_loss_grad(self.handle, _buf(xy, "xy", torch.int32, n * 2, dev),
+                                         _buf(target, "target", torch.float32, n * 4, dev), n,
                                          precision, _dptr(loss), _dptr(grad), _stream(stream)))
         return loss, grad
 
     def train(self, target: Texture, steps, batch=65536, lr=1e-3, seed=0, precision=BF16,
               loss_trace=None, stream=None):
+        import torch
+        trace = _buf(loss_trace, "loss_trace", torch.float32, max(0, steps), self.ctx.device)
         _check(lib.ctf_decoder_train(self.handle, target.handle, steps, batch, lr,
-                                     seed & (2**64 - 1), precision, _dptr(loss_trace),
-                                     _stream(stream)))
+                                     seed & (2**64 - 1), precision, trace, _stream(stream)))
 
     def close(self):
         if self.handle:
@@ -300,15 +356,18 @@ class Decoder:
             self.handle = None
 
 
-def tile_stats_buffer(sw, sh, device="cuda", tile_h=8):
+def tile_stats_buffer(sw, sh, device="cuda", tile_h=None, meth: Optional[Method] = None, layers=1):
+    """Zeroed tile records for a frame: the tile height follows the method's
+    wave shape (8x4 waves write twice the tile rows of 8x8 waves)."""
     import torch
-    tiles = ((sw + 7) // 8) * ((sh + tile_h - 1) // tile_h)
-    return torch.zeros((tiles, TILE_STATS_DTYPE.itemsize), dtype=torch.uint8, device=device)
+    th = tile_h if tile_h is not None else tile_height(meth)
+    tiles = ((sw + 7) // 8) * ((sh + th - 1) // th)
+    return torch.zeros((layers * tiles, TILE_STATS_DTYPE.itemsize), dtype=torch.uint8, device=device)
 
 
 def frame_stats_buffer(device="cuda"):
     import torch
-    return torch.zeros(16, dtype=torch.int64, device=device)
+    return torch.zeros(FRAME_STATS_WORDS, dtype=torch.int64, device=device)
 
 
 def tile_stats_numpy(buf) -> np.ndarray:
@@ -320,9 +379,10 @@ def frame_stats_dict(buf) -> dict:
     return {k: int(v[i]) for i, k in enumerate(FRAME_STATS_FIELDS)}
 
 
-def lists_buffer(sw, sh, device="cuda", tile_h=8):
+def lists_buffer(sw, sh, device="cuda", tile_h=None, meth: Optional[Method] = None):
     import torch
-    tiles = ((sw + 7) // 8) * ((sh + tile_h - 1) // tile_h)
+    th = tile_h if tile_h is not None else tile_height(meth)
+    tiles = ((sw + 7) // 8) * ((sh + th - 1) // th)
     return torch.full((tiles, MAX_ITEMS, 2), -2**31, dtype=torch.int32, device=device)
 
 

@@ -100,3 +100,63 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 7, r.stdout + r.stderr
     assert "no CPU fallback" in r.stdout
+
+
+class _FakeDev:
+    def __init__(self, index):
+        self.index = index
+
+
+class _FakeTensor:
+    """Stands in for a device tensor: the binding's buffer checks read only
+    these attributes (no GPU here)."""
+
+    def __init__(self, numel, dtype, device=0, contiguous=True, cuda=True, itemsize=4):
+        self._n, self.dtype, self.device = numel, dtype, _FakeDev(device)
+        self._c, self.is_cuda, self._s = contiguous, cuda, itemsize
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._s
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_checks_caller_buffers():
+    """A buffer the library would write past, or read with the wrong type or
+    on another device, is refused before the call."""
+    import pytest
+    import torch
+    import paper_2506_17770_amd as ctf
+    f32 = torch.float32
+    assert ctf._buf(None, "x", f32, 10, 0) is None
+    assert ctf._buf(_FakeTensor(10, f32), "x", f32, 10, 0) == 4096
+    bad = [_FakeTensor(9, f32),                     # too short
+           _FakeTensor(10, torch.int32),            # wrong dtype
+           _FakeTensor(10, f32, device=1),          # another device
+           _FakeTensor(10, f32, contiguous=False),
+           _FakeTensor(10, f32, cuda=False)]
+    for t in bad:
+        with pytest.raises(ctf.CtfError):
+            ctf._buf(t, "x", f32, 10, 0)
+    # byte-counted buffers (tile records)
+    assert ctf._buf(_FakeTensor(128, torch.uint8, itemsize=1), "ts", None, 128, 0) == 4096
+    with pytest.raises(ctf.CtfError):
+        ctf._buf(_FakeTensor(127, torch.uint8, itemsize=1), "ts", None, 128, 0)
+
+
+def test_tile_buffers_follow_the_wave_shape():
+    """8x4 waves write a record per 8x4 tile: twice the rows of 8x8 tiles."""
+    import paper_2506_17770_amd as ctf
+    m8, m4 = ctf.method(ctf.LIST), ctf.method(ctf.LIST, wave_shape=ctf.WAVE_8X4)
+    assert ctf.n_tiles(203, 77, m8) == 26 * 10 and ctf.n_tiles(203, 77, m4) == 26 * 20
+    assert ctf.tile_stats_buffer(203, 77, device="cpu", meth=m4).shape == (26 * 20, 128)
+    assert ctf.tile_stats_buffer(203, 77, device="cpu", meth=m8).shape == (26 * 10, 128)
+    assert ctf.lists_buffer(203, 77, device="cpu", meth=m4).shape == (26 * 20, ctf.MAX_ITEMS, 2)
+    assert ctf.tile_stats_buffer(203, 77, device="cpu", meth=m8, layers=6).shape == (6 * 26 * 10, 128)
