@@ -209,7 +209,7 @@ def method(kind, box=(0, 0), mask_side=16, k=1, fallback=FB_STF1, filter=FILTER_
 
 
 def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 8),
-           tiles=None, stats=True, lists=False, stf=False, xform=None, fb_items=False):
+           tiles=None, stats=True, lists=False, stf=False, xform=None, fb_items=False, into=None):
     """Run the oracle filter.  Returns dict(out f64 [H][W][4], stats, lists, stf, fb_items).
 
     ``tiles`` = (begin, end) restricts the work to a tile range (the other
@@ -224,10 +224,11 @@ def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 
     sh, sw = uv.shape[:2]
     tw, th = tile
     ntiles = ((sw + tw - 1) // tw) * ((sh + th - 1) // th)
-    out = np.zeros((sh, sw, 4), np.float64)
-    st = np.zeros(ntiles, TILE_STATS_DTYPE) if stats else None
+    # preallocated outputs (filter_parallel): each call writes only its tiles
+    out = into["out"] if into else np.zeros((sh, sw, 4), np.float64)
+    st = (into["stats"] if into else np.zeros(ntiles, TILE_STATS_DTYPE)) if stats else None
     li = np.full((ntiles, MAX_ITEMS, 2), np.iinfo(np.int32).min, np.int32) if lists else None
-    sx = np.full((sh, sw, 2), np.iinfo(np.int32).min, np.int32) if stf else None
+    sx = (into["stf"] if into else np.full((sh, sw, 2), np.iinfo(np.int32).min, np.int32)) if stf else None
     fi = np.full((ntiles, MAX_FB_ITEMS, 3), np.iinfo(np.int32).min, np.int32) if fb_items else None
     b, e = tiles if tiles is not None else (0, ntiles)
     rc = lib().ctfo_filter(_ptr(uv), _ptr(duv), sw, sh, tw, th, ctypes.byref(tex.struct),
@@ -236,6 +237,40 @@ def filter(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 
     if rc:
         raise RuntimeError(f"ctfo_filter failed ({rc})")
     return dict(out=out, stats=st, lists=li, stf=sx, fb_items=fi)
+
+
+def filter_parallel(uv, duv, tex: OracleTexture, meth: Method, seed=0, layer=0, tile=(8, 8),
+                    stf=True, xform=None, threads=None):
+    """The whole frame through ``filter`` on several host threads, each on a
+    contiguous range of tiles (the C oracle releases the GIL; tiles are
+    independent).  Returns dict(out, stats, stf) as ``filter`` does."""
+    import threading
+    sh, sw = np.asarray(uv).shape[:2]
+    tw, th = tile
+    ntiles = ((sw + tw - 1) // tw) * ((sh + th - 1) // th)
+    into = {"out": np.zeros((sh, sw, 4), np.float64), "stats": np.zeros(ntiles, TILE_STATS_DTYPE),
+            "stf": np.full((sh, sw, 2), np.iinfo(np.int32).min, np.int32)}
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    duv = np.ascontiguousarray(duv, dtype=np.float32)
+    n = max(1, min(threads or os.cpu_count() or 1, 16, ntiles))
+    bounds = np.linspace(0, ntiles, n + 1).astype(np.int64)
+    errs = []
+
+    def work(b, e):
+        try:
+            filter(uv, duv, tex, meth, seed=seed, layer=layer, tile=tile, tiles=(int(b), int(e)), stats=True,
+                   stf=stf, xform=xform, into=into)
+        except Exception as ex:   # surfaced below
+            errs.append(ex)
+
+    ths = [threading.Thread(target=work, args=(bounds[i], bounds[i + 1])) for i in range(n)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    if errs:
+        raise errs[0]
+    return dict(out=into["out"], stats=into["stats"], stf=into["stf"] if stf else None)
 
 
 def decoder_loss_grad(params, xy, target, l0, l1, hidden, tex_w, channels=8, grad=True):

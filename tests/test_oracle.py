@@ -780,3 +780,17 @@ def test_cplus_spare_draws_follow_abs_weights():
     assert pit.size > 10000
     counts = np.histogram(pit, bins=20, range=(0, 1))[0]
     assert chisquare(counts).pvalue > 1e-4, counts
+
+
+def test_filter_parallel_equals_one_call():
+    """The threaded whole-frame helper the full-frame GPU tests use gives
+    the single call's outputs bit for bit (8x8 and 8x4 tiles, a fallback)."""
+    sc = cs.random_planes_scene(203, 77, 64, 64, seed=4)
+    pqj, amp = cs.sinusoid_params(64, 8, 8, seed=1)
+    tex = O.sinusoid_texture(64, pqj, amp)
+    for m, t in ((O.method(O.LIST, k=2), (8, 8)), (O.method(O.MASK, fallback=O.FB_CPLUS), (8, 4)),
+                 (O.method(O.BILINEAR4, filter=O.FILTER_CATMULL_ROM), (8, 8))):
+        a = O.filter(sc.uv, sc.duv, tex, m, seed=3, stf=True, tile=t)
+        b = O.filter_parallel(sc.uv, sc.duv, tex, m, seed=3, tile=t, threads=5)
+        for k in ("out", "stats", "stf"):
+            assert np.array_equal(a[k], b[k]), k
