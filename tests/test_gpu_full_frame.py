@@ -109,7 +109,7 @@ def test_full_frame_layers_4k(G, prec):
             assert np.array_equal(sx[l], o["stf"]), f"layer {l} kind {gk}: draws differ"
             stats.append(o["stats"])
         st = np.concatenate(stats)
-        pc = lambda a: int(np.unpackbits(a.view(np.uint8)).sum())
+        pc = lambda a: int(np.unpackbits(np.ascontiguousarray(a).view(np.uint8)).sum())
         assert fr["evals"] == int(st["evals"].sum())
         assert fr["active"] == pc(st["active"]) and fr["stf"] == pc(st["stf"])
         assert fr["minify"] == pc(st["active"] & ~st["part"])
