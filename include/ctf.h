@@ -307,6 +307,30 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder dec, const int32_t *xy, const float
                                  int32_t n, int32_t precision, float *loss, float *grad,
                                  void *stream);
 
+/* Most samples one ctf_decoder_loss_grad_noalloc call takes. */
+#define CTF_NOALLOC_MAX_SAMPLES 16384
+
+/* ctf_decoder_loss_grad without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc.  Arguments, results and precision
+ * as for ctf_decoder_loss_grad (the same kernels in the same order, so the
+ * loss and gradient are bitwise equal to that call's); the caller still
+ * provides xy, target, loss and grad (device memory).
+ * Scratch: a fixed array the library holds on each device from the first
+ * ctf_create on that device until the process ends (5.8 MB: per-wave
+ * partial sums of one pass over at most CTF_NOALLOC_MAX_SAMPLES samples of a
+ * decoder with hidden width <= 64), instead of the decoder's batch buffers.
+ * Every call on a device uses that device's one array and each pass writes
+ * every scratch entry it reads, so nothing carries over from an earlier
+ * call; calls that overlap on one device (other streams, other threads,
+ * other decoders) race on the array and must be serialised by the caller.
+ * Errors: CTF_ERR_INVALID_ARG (NULL buffers, n <= 0 or n above
+ * CTF_NOALLOC_MAX_SAMPLES, bad precision), CTF_ERR_DEVICE (no scratch
+ * address for the decoder's device). */
+ctf_status ctf_decoder_loss_grad_noalloc(ctf_decoder dec, const int32_t *xy, const float *target,
+                                         int32_t n, int32_t precision, float *loss, float *grad,
+                                         void *stream);
+
 /* Train with Adam (beta 0.9/0.999, eps 1e-8) for `steps` steps of `batch`
  * texels drawn uniformly from the lattice by the pcg hash of (seed, step,
  * sample); targets are produced by `target` (any texel producer).

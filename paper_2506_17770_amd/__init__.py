@@ -86,6 +86,7 @@ SIGNATURES = {
     "ctf_decoder_get_state": (_I32, [_P, _P, _SZ]),
     "ctf_decoder_set_state": (_I32, [_P, _P, _SZ]),
     "ctf_decoder_loss_grad": (_I32, [_P, _P, _P, _I32, _I32, _P, _P, _P]),
+    "ctf_decoder_loss_grad_noalloc": (_I32, [_P, _P, _P, _I32, _I32, _P, _P, _P]),
     "ctf_decoder_train": (_I32, [_P, _P, _I64, _I32, _F, _U64, _I32, _P, _P]),
 }
 
@@ -342,6 +343,18 @@ class Decoder:
                                          _buf(target, "target", torch.float32, n * 4, dev), n,
                                          precision, _dptr(loss), _dptr(grad), _stream(stream)))
         return loss, grad
+
+    def loss_grad_noalloc(self, xy, target, loss, grad, precision=BF16, stream=None):
+        """ctf_decoder_loss_grad_noalloc: the caller provides loss (float32 [1])
+        and grad (float32 [param_count]); the library allocates nothing."""
+        import torch
+        if xy.dim() != 2 or xy.shape[1] != 2:
+            raise CtfError("xy must be [n][2]")
+        n, dev = xy.shape[0], self.ctx.device
+        _check(lib.ctf_decoder_loss_grad_noalloc(
+            self.handle, _buf(xy, "xy", torch.int32, n * 2, dev), _buf(target, "target", torch.float32, n * 4, dev),
+            n, precision, _buf(loss, "loss", torch.float32, 1, dev), _buf(grad, "grad", torch.float32, self.count, dev),
+            _stream(stream)))
 
     def train(self, target: Texture, steps, batch=65536, lr=1e-3, seed=0, precision=BF16,
               loss_trace=None, stream=None):

@@ -95,6 +95,12 @@ ctf_status ctf_create(int device, ctf_context* out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(CTF_ERR_UNSUPPORTED, "ctf_create: device %d is %s, this library is built for gfx950",
                     device, prop.gcnArchName);
+    {
+        DeviceScope ds(device);
+        if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_create: set device");
+        e = noalloc_scratch_init(device);
+        if (e != hipSuccess) return hip_fail(e, "ctf_create: scratch address");
+    }
     ctf_context c = new (std::nothrow) ctf_context_s;
     if (!c) return fail(CTF_ERR_OUT_OF_MEMORY, "ctf_create: host allocation");
     c->device = device;

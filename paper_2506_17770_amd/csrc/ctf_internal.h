@@ -51,6 +51,10 @@ hipError_t launch_texel_eval_simt(const DevTexture& T, const int32_t* xy, int64_
 
 void set_error(const std::string& msg);
 
+// Looks up the device address of the allocation-free call's scratch array
+// for `device` (which must be current); done once per device.
+hipError_t noalloc_scratch_init(int device);
+
 }  // namespace ctf
 
 struct ctf_context_s {

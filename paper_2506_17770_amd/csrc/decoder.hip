@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -88,51 +89,49 @@ struct ctf_decoder_s {
 
 namespace ctf {
 
-// Packed positions of flat MLP parameter `rel` (relative to W1): weight
-// entries map to one forward and one backward element of w_lp; biases map
-// to 16 float slots of bias_c.  Returns the number of positions.
-__host__ __device__ inline int packed_targets(int rel, int H, int* pos, bool* is_bias)
+// Packed positions of flat MLP parameter `rel` (relative to W1): a weight
+// entry has one forward and one backward element of w_lp (weight(pos) is
+// called for each); a bias has 16 float slots of bias_c (bias(pos) for
+// each).  Positions are produced one at a time (no indexed local array, so
+// the kernels using this need no private memory).
+template <class OnWeight, class OnBias>
+__host__ __device__ inline void packed_visit(int rel, int H, OnWeight&& weight, OnBias&& bias)
 {
     const int nW1 = 16 * H, nW2 = H * H, nW3 = H * 4;
-    *is_bias = false;
     if (rel < nW1) {
         const int f = rel / H, h = rel % H;
-        pos[0] = kW1T + ((h >> 4) * 64 + (f >> 2) * 16 + (h & 15)) * 4 + (f & 3);
-        pos[1] = kW1A + (kc_of(h) * 64 + g_of(h) * 16 + f) * 8 + s_of(h);
-        return 2;
+        weight(kW1T + ((h >> 4) * 64 + (f >> 2) * 16 + (h & 15)) * 4 + (f & 3));
+        weight(kW1A + (kc_of(h) * 64 + g_of(h) * 16 + f) * 8 + s_of(h));
+        return;
     }
     rel -= nW1;
     if (rel < H) {
         const int h = rel;
-        *is_bias = true;
-        for (int j = 0; j < 16; ++j) pos[j] = kB1C + ((h >> 4) * 64 + ((h & 15) >> 2) * 16 + j) * 4 + (h & 3);
-        return 16;
+        for (int j = 0; j < 16; ++j) bias(kB1C + ((h >> 4) * 64 + ((h & 15) >> 2) * 16 + j) * 4 + (h & 3));
+        return;
     }
     rel -= H;
     if (rel < nW2) {
         const int i = rel / H, o = rel % H;
-        pos[0] = kW2T + (((o >> 4) * 2 + kc_of(i)) * 64 + g_of(i) * 16 + (o & 15)) * 8 + s_of(i);
-        pos[1] = kW2A + (((i >> 4) * 2 + kc_of(o)) * 64 + g_of(o) * 16 + (i & 15)) * 8 + s_of(o);
-        return 2;
+        weight(kW2T + (((o >> 4) * 2 + kc_of(i)) * 64 + g_of(i) * 16 + (o & 15)) * 8 + s_of(i));
+        weight(kW2A + (((i >> 4) * 2 + kc_of(o)) * 64 + g_of(o) * 16 + (i & 15)) * 8 + s_of(o));
+        return;
     }
     rel -= nW2;
     if (rel < H) {
         const int o = rel;
-        *is_bias = true;
-        for (int j = 0; j < 16; ++j) pos[j] = kB2C + ((o >> 4) * 64 + ((o & 15) >> 2) * 16 + j) * 4 + (o & 3);
-        return 16;
+        for (int j = 0; j < 16; ++j) bias(kB2C + ((o >> 4) * 64 + ((o & 15) >> 2) * 16 + j) * 4 + (o & 3));
+        return;
     }
     rel -= H;
     if (rel < nW3) {
         const int h = rel / 4, c = rel % 4;
-        pos[0] = kW3T + (kc_of(h) * 64 + g_of(h) * 16 + c) * 8 + s_of(h);
-        pos[1] = kW3A + ((h >> 4) * 64 + (h & 15)) * 4 + c;
-        return 2;
+        weight(kW3T + (kc_of(h) * 64 + g_of(h) * 16 + c) * 8 + s_of(h));
+        weight(kW3A + ((h >> 4) * 64 + (h & 15)) * 4 + c);
+        return;
     }
     rel -= nW3;
-    *is_bias = true;
-    for (int j = 0; j < 16; ++j) pos[j] = kB3C + j * 4 + rel;
-    return 16;
+    for (int j = 0; j < 16; ++j) bias(kB3C + j * 4 + rel);
 }
 
 // Host packing (inference textures and the first training copy).
@@ -162,15 +161,9 @@ void pack_host(const float* P, const ctf_decoder_desc& d, int precision, std::ve
     for (int64_t i = 0; i < lay.mlp0; ++i) lat[i] = cvt(P[i]);
     w.assign(kAllElems, 0);
     bias.assign(kBiasFloats, 0.f);
-    int pos[16];
-    bool is_bias;
     for (int64_t r = 0; r < lay.mlp_count; ++r) {
-        const int n = packed_targets((int)r, d.hidden, pos, &is_bias);
         const float val = P[lay.mlp0 + r];
-        for (int k = 0; k < n; ++k) {
-            if (is_bias) bias[pos[k]] = val;
-            else w[pos[k]] = cvt(val);
-        }
+        packed_visit((int)r, d.hidden, [&](int q) { w[q] = cvt(val); }, [&](int q) { bias[q] = val; });
     }
 }
 
@@ -554,13 +547,8 @@ __global__ void k_adam(AdamArgs a)
     if (p < a.mlp0) {
         a.lat_lp[p] = Mfma<P>::cvt(th);
     } else {
-        int pos[16];
-        bool is_bias;
-        const int n = packed_targets((int)(p - a.mlp0), a.hidden, pos, &is_bias);
-        if (is_bias)
-            for (int k = 0; k < n; ++k) a.bias_c[pos[k]] = th;
-        else
-            for (int k = 0; k < n; ++k) a.w_lp[pos[k]] = Mfma<P>::cvt(th);
+        const uint16_t lp = Mfma<P>::cvt(th);
+        packed_visit((int)(p - a.mlp0), a.hidden, [&](int q) { a.w_lp[q] = lp; }, [&](int q) { a.bias_c[q] = th; });
     }
 }
 
@@ -646,6 +634,15 @@ int train_waves(int n)
     return waves < kTrainWaves ? kTrainWaves : waves;
 }
 
+// Scratch of one loss/gradient pass: per-wave partial sums [waves][mlp_count],
+// per-wave losses [waves] and the reduction slices [waves / kSlice][mlp_count
+// + 1].  Every entry a pass reads is written by the same pass first.
+struct PassScratch {
+    float* partials;
+    float* loss_part;
+    float* slices;
+};
+
 hipError_t ensure_batch(ctf_decoder d, int32_t n)
 {
     if (n <= d->cap_batch) return hipSuccess;
@@ -666,6 +663,8 @@ hipError_t ensure_batch(ctf_decoder d, int32_t n)
     if (e == hipSuccess) d->cap_batch = n;
     return e;
 }
+
+PassScratch batch_scratch(ctf_decoder d) { return PassScratch{d->partials, d->loss_part, d->slices}; }
 
 template <int P, bool UPDATE>
 hipError_t launch_adam(ctf_decoder d, float lr, hipStream_t s)
@@ -713,7 +712,8 @@ hipError_t ensure_lp(ctf_decoder d, int precision, hipStream_t s)
 // them once and then relies on the Adam step, which zeroes what it reads.
 template <int P>
 hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target, int32_t n,
-                          float* loss, float* grad, bool latent_to_grad, bool zero_latent, hipStream_t s)
+                          float* loss, float* grad, bool latent_to_grad, bool zero_latent,
+                          const PassScratch& sc, hipStream_t s)
 {
     const Layout& L = d->lay;
     const int fb = 1024;
@@ -729,23 +729,68 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
     a.n = n;
     a.gscale = 2.0f / (4.0f * (float)n);
     a.glat = d->glat_fx;
-    a.partials = d->partials;
-    a.loss_part = d->loss_part;
+    a.partials = sc.partials;
+    a.loss_part = sc.loss_part;
     a.mlp_count = (int)L.mlp_count;
     const int waves = train_waves(n);
     hipLaunchKernelGGL((k_train<P>), dim3(waves / kTrainWaves), dim3(64 * kTrainWaves), 0, s, a);
     const int rb = 256;
     const int nsl = (waves + kSlice - 1) / kSlice;
     const unsigned gx = (unsigned)((L.mlp_count + 1 + rb - 1) / rb);
-    hipLaunchKernelGGL(k_reduce1, dim3(gx, (unsigned)nsl), dim3(rb), 0, s, d->partials, d->loss_part, waves,
-                       (int)L.mlp_count, d->slices);
-    hipLaunchKernelGGL(k_reduce2, dim3(gx), dim3(rb), 0, s, d->slices, nsl, (int)L.mlp_count,
+    hipLaunchKernelGGL(k_reduce1, dim3(gx, (unsigned)nsl), dim3(rb), 0, s, sc.partials, sc.loss_part, waves,
+                       (int)L.mlp_count, sc.slices);
+    hipLaunchKernelGGL(k_reduce2, dim3(gx), dim3(rb), 0, s, sc.slices, nsl, (int)L.mlp_count,
                        grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
     if (latent_to_grad) hipLaunchKernelGGL(k_fx_to_float, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0, grad);
     return hipGetLastError();
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free loss/gradient call.  One fixed array per
+// device (the code object's own copy), sized for CTF_NOALLOC_MAX_SAMPLES
+// samples of a decoder with hidden width <= 64: the per-wave partial sums,
+// per-wave losses and reduction slices of one pass (PassScratch).  Host code
+// never passes `scratch` itself to a kernel: its device address is looked up
+// once per device at context creation (ctf_create) and kept in
+// g_scratch_dev.  Calls on one device share the array.
+// ---------------------------------------------------------------------------
+
+constexpr int kNoAllocWaves = 256;   // train_waves(CTF_NOALLOC_MAX_SAMPLES)
+constexpr int kNoAllocMlp = 16 * kHid + kHid + kHid * kHid + kHid + kHid * 4 + 4;
+constexpr int kNoAllocSlices = (kNoAllocWaves + kSlice - 1) / kSlice;
+constexpr size_t kNoAllocPartials = (size_t)kNoAllocWaves * kNoAllocMlp;
+constexpr size_t kNoAllocFloats = kNoAllocPartials + kNoAllocWaves + (size_t)kNoAllocSlices * (kNoAllocMlp + 1);
+constexpr int kMaxScratchDevices = 64;
+
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxScratchDevices] = {};
+
+float* scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+}  // namespace
+
+// Called by ctf_create with `device` current.
+hipError_t ctf::noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = static_cast<float*>(p);
+    return hipSuccess;
+}
 
 extern "C" {
 
@@ -896,9 +941,34 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder d, const int32_t* xy, const float* 
     hipError_t e = ensure_batch(d, n);
     if (e == hipSuccess) e = ensure_lp(d, precision, s);
     if (e == hipSuccess)
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, true, s)
-                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, true, s);
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, true, batch_scratch(d), s)
+                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, true, batch_scratch(d), s);
     return e == hipSuccess ? CTF_OK : hip_fail(e, "ctf_decoder_loss_grad");
+}
+
+ctf_status ctf_decoder_loss_grad_noalloc(ctf_decoder d, const int32_t* xy, const float* target, int32_t n,
+                                         int32_t precision, float* loss, float* grad, void* stream)
+{
+    set_error("");
+    if (!d || !xy || !target || !loss || !grad || n <= 0)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_loss_grad_noalloc: bad arguments");
+    if (n > CTF_NOALLOC_MAX_SAMPLES)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_loss_grad_noalloc: n above CTF_NOALLOC_MAX_SAMPLES");
+    if (precision != CTF_BF16 && precision != CTF_FP16)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_loss_grad_noalloc: precision");
+    if (train_waves(n) > kNoAllocWaves || d->lay.mlp_count > kNoAllocMlp)
+        return fail(CTF_ERR_INVALID_ARG, "ctf_decoder_loss_grad_noalloc: pass does not fit the scratch array");
+    float* base = scratch_address(d->ctx->device);
+    if (!base) return fail(CTF_ERR_DEVICE, "ctf_decoder_loss_grad_noalloc: scratch address of the device not set up");
+    DeviceScope ds(d->ctx->device);
+    if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_loss_grad_noalloc: set device");
+    hipStream_t s = (hipStream_t)stream;
+    const PassScratch sc{base, base + kNoAllocPartials, base + kNoAllocPartials + kNoAllocWaves};
+    hipError_t e = ensure_lp(d, precision, s);
+    if (e == hipSuccess)
+        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, true, sc, s)
+                                  : loss_grad_impl<CTF_FP16>(d, xy, target, n, loss, grad, true, true, sc, s);
+    return e == hipSuccess ? CTF_OK : hip_fail(e, "ctf_decoder_loss_grad_noalloc");
 }
 
 ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, int32_t batch, float lr,
@@ -943,8 +1013,9 @@ ctf_status ctf_decoder_train(ctf_decoder d, ctf_texture target, int64_t steps, i
             hipLaunchKernelGGL(k_sample<CTF_TEX_TABLE>, sg, dim3(sb), 0, s, T, seed, st, batch, d->desc.tex_w, xy, tg);
         }
         float* lt = loss_trace ? loss_trace + it : d->loss_tmp;
-        e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, false, false, s)
-                                  : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, false, false, s);
+        e = precision == CTF_BF16
+                ? loss_grad_impl<CTF_BF16>(d, d->xy, d->target, batch, lt, d->grad, false, false, batch_scratch(d), s)
+                : loss_grad_impl<CTF_FP16>(d, d->xy, d->target, batch, lt, d->grad, false, false, batch_scratch(d), s);
         if (e != hipSuccess) break;
         d->step += 1;
         e = precision == CTF_BF16 ? launch_adam<CTF_BF16, true>(d, lr, s) : launch_adam<CTF_FP16, true>(d, lr, s);
