@@ -152,6 +152,12 @@ __device__ __forceinline__ void decode_rows(DecLds& L, int R, const InferGrid& G
         fetch_row<P>(L.rows, 16 * (t + 2) + j, G, K, fa);
         finish_row<P>(L.vals, R, 16 * (t + 1) + j, W, Bz, fb, g);
     }
+    // The last prefetch (issued during the last MLP) is never used: wait for
+    // it here, while it is nearly done, rather than where its registers are
+    // next written, which may be after the next tile's inputs were requested
+    // (memory counters drain in order, so that wait would cover them too).
+    asm volatile("" ::"v"(fa.v[0]), "v"(fa.v[1]), "v"(fa.v[2]), "v"(fa.v[3]), "v"(fb.v[0]), "v"(fb.v[1]),
+                 "v"(fb.v[2]), "v"(fb.v[3]));
 }
 
 __device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t tile, uint64_t act, uint64_t A,
@@ -180,11 +186,13 @@ __device__ __forceinline__ void write_tile_stats(const FilterArgs& a, int64_t ti
 // One tile of the decoder-path filter: decisions, row list, MFMA decode,
 // gather and outputs.  `f` is the lanes' footprint (already in this
 // layer's coordinates); a.out / a.tile_stats / a.stf_xy point at this
-// layer's planes.
-template <int METHOD, int P, bool STATS, bool FB, int FILTER>
+// layer's planes.  `after_decode` runs once, right after the tile's (first)
+// decode pass: the caller requests the next tile's inputs there, so that no
+// wait for the decode's latent loads covers them.
+template <int METHOD, int P, bool STATS, bool FB, int FILTER, class AfterDecode>
 __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G, const FwdWeights<P>& W,
                                          const Biases& Bz, DecLds& L, int64_t tile, int tx, int ty,
-                                         const Footprint& f, FrameCounters& fc)
+                                         const Footprint& f, FrameCounters& fc, AfterDecode&& after_decode)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
     const int lane = lane_id();
@@ -293,6 +301,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
             }
             wave_lds_sync();
             decode_rows<P>(L, R, G, W, Bz, j, g);
+            if (jr == 0) after_decode();
             wave_lds_sync();
             if (exact) {
                 float wx[4], wy[4];
@@ -406,6 +415,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
     // ---- decode the rows, 16 per MFMA tile; the latent gathers of the
     // next tile are in flight during the MLP of the current one
     decode_rows<P>(L, R, G, W, Bz, j, g);
+    after_decode();
     wave_lds_sync();
 
     // ---- gather and weight
@@ -520,6 +530,17 @@ __device__ __forceinline__ void load_tile_px_s(const FilterArgs& a, const TileWa
     }
 }
 
+// Wait for the first tile's inputs before entering a tile loop.  The loop
+// loads each next tile's inputs one tile ahead and copies them at the top of
+// the next iteration; without this, the loads issued before the loop are
+// still pending into the registers the first iteration reads, and the
+// memory-counter wait placed at the loop head (counters drain in order)
+// would also wait for the prefetch issued in every later iteration.
+__device__ __forceinline__ void settle(const float2& uv, const float4& d)
+{
+    asm volatile("" ::"v"(uv.x), "v"(uv.y), "v"(d.x), "v"(d.y), "v"(d.z), "v"(d.w));
+}
+
 // XCD-aware band of tiles for this wave: workgroups go round-robin over the
 // 8 XCDs, so band b of the screen is walked by the workgroups of XCD b.
 struct Band {
@@ -569,14 +590,16 @@ __global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>
     float4 d_next;
     TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
     load_tile_px(a, next, band.end, uv_next, d_next);
+    settle(uv_next, d_next);
     while (next.tile < band.end) {
         const TileWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
-        next.advance(band.nw);
-        load_tile_px(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
-        dec_tile<METHOD, P, STATS, FB, FILTER>(a, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
+        dec_tile<METHOD, P, STATS, FB, FILTER>(a, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc, [&] {
+            next.advance(band.nw);
+            load_tile_px(a, next, band.end, uv_next, d_next);
+        });
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);
 }
@@ -867,14 +890,14 @@ __device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, B
 }
 
 // Plan a tile and append its rows to the batch (decoding the batch first
-// when it is full or the rows do not fit behind it).
+// when the rows do not fit behind it).  The caller decodes a full batch (two
+// tiles) before calling.
 template <int METHOD, int P, bool STATS>
 __device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Batch& bt, const InferGrid& G,
                                           const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc,
                                           const TileWalk& cur, const Footprint& f)
 {
     const int lane = lane_id();
-    if (bt.npend == 2) batch_flush<METHOD, P>(a, BL, bt, G, W, Bz, fc);
     const int R = plan_tile<METHOD, STATS>(a, BL, bt.npend, bt.rows, cur.tile, cur.tx, cur.ty, f, fc);
     if (bt.rows + R > kMaxItems) {
         // planned into slot 1 with its rows staged: decode slot 0, then move
@@ -914,10 +937,15 @@ __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterAr
     float4 d_next;
     TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
     load_tile_px_s(a, next, band.end, uv_next, d_next);
+    settle(uv_next, d_next);
     while (next.tile < band.end) {
         const TileWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
+        // decode a full batch first, then request the next tile's inputs:
+        // their latency is hidden by this tile's planning and the next
+        // iteration's decode, and no wait inside the decode covers them
+        if (bt.npend == 2) batch_flush<METHOD, P>(a, BL, bt, D.grid, W, Bz, fc);
         next.advance(band.nw);
         load_tile_px_s(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
@@ -1039,18 +1067,20 @@ k_filter_layers(FilterArgs a, LayerSet LS)
         float4 d_next;
         TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
         load_tile_px(a, next, band.end, uv_next, d_next);
+        settle(uv_next, d_next);
         while (next.tile < band.end) {
             const TileWalk cur = next;
             const float2 uv = uv_next;
             const float4 d = d_next;
-            next.advance(band.nw);
-            load_tile_px(a, next, band.end, uv_next, d_next);
             // layer coordinates, float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u)
             const float lu = __builtin_fmaf(m01, uv.y, m00 * uv.x), lv = __builtin_fmaf(m11, uv.y, m10 * uv.x);
             const float4 ld = make_float4(__builtin_fmaf(m01, d.y, m00 * d.x), __builtin_fmaf(m11, d.y, m10 * d.x),
                                           __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
             const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
-            dec_tile<METHOD, P, STATS, FB, FILTER>(al, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc);
+            dec_tile<METHOD, P, STATS, FB, FILTER>(al, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc, [&] {
+                next.advance(band.nw);
+                load_tile_px(a, next, band.end, uv_next, d_next);
+            });
         }
     }
     if (lane == 0 && a.frame_stats) fc.flush(a.frame_stats);

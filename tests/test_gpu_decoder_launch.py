@@ -70,6 +70,7 @@ def popcount(a):
 def check_frame(g, o, collaborative, what, tol=TOL):
     assert np.array_equal(g["stf"], o["stf"]), f"{what}: draws differ"
     err = np.abs(g["out"].astype(np.float64) - o["out"])
+    print(f"colour error {what}: {err.max():.3e}", flush=True)
     assert err.max() <= tol, f"{what}: colour error {err.max():.3e}"
     st, fr = o["stats"], g["frame"]
     assert fr["evals"] == int(st["evals"].sum()), what

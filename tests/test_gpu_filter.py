@@ -67,6 +67,7 @@ def compare(g, o, what="", tol=TOL):
         assert np.array_equal(g["lists"][t, :n], o["lists"][t, :n]), f"{what}: list of tile {t}"
     assert np.array_equal(g["stf"], o["stf"]), f"{what}: STF draws differ"
     err = np.abs(g["out"].astype(np.float64) - o["out"])
+    print(f"colour error {what}: {err.max():.3e}", flush=True)
     assert err.max() <= tol, f"{what}: max colour error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
     st = o["stats"]
     fr = g["frame"]
