@@ -83,7 +83,6 @@ struct ctf_decoder_s {
     float* target = nullptr;
     float* partials = nullptr;     // [max waves][mlp_count]
     float* loss_part = nullptr;    // [max waves]
-    float* slices = nullptr;       // [max waves / kSlice][mlp_count + 1]
     float* loss_tmp = nullptr;     // [1]
 };
 
@@ -243,7 +242,7 @@ struct TrainArgs {
     const float4* target;
     int n;                    // samples
     float gscale;             // 2 / (4 n)
-    int64_t* glat;            // latent gradient, fixed point (flat, atomics), may be null
+    int64_t* glat;            // latent gradient, fixed point (flat, atomics)
     float* partials;          // [waves][mlp_count]
     float* loss_part;         // [waves]
     int mlp_count;
@@ -268,14 +267,27 @@ __device__ __forceinline__ u16x4 read_T(const uint16_t* slot, int lane)
     return *reinterpret_cast<const u16x4*>(slot + h * 16 + 4 * g);
 }
 
+// Latent-gradient scatter of one 16-sample tile, staged through LDS so that
+// the 8 lanes of each group cover the 8 channels of one latent cell: one
+// atomic instruction then touches 8 cache lines instead of 32 (the memory
+// system's atomic rate is per line).  Staging per wave: dx [16][2][8] floats,
+// corner weights [16][2][4] floats and cells [16][2][4].
+struct GradStage {
+    float dx[16][2][8];
+    float w[16][2][4];
+    uint32_t cell[16][2][4];
+};
+
 template <int P>
 __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
 {
     __shared__ uint16_t lds[kTrainWaves][18][256];
+    __shared__ GradStage gst[kTrainWaves];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
     uint16_t(*S)[256] = lds[wid];
+    GradStage& GS = gst[wid];
     const int gw = blockIdx.x * kTrainWaves + wid;
     const int nw = gridDim.x * kTrainWaves;
 
@@ -305,13 +317,30 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
     }
     float loss = 0.f;
 
+    // Inputs of a tile: sample coordinates one tile ahead, latent corners and
+    // targets requested during the previous tile, before its atomics (the
+    // memory counters complete in order, so a wait for loads issued after the
+    // atomics would wait for the atomics too).  Every load is unconditional
+    // (an index past the batch reads the last sample, n >= 1): a load skipped
+    // on some path would make the loop head's wait count for the worst path.
+    // A padded sample's features are zeroed, so its gradients are exact
+    // zeros and its atomics add nothing.
     const int ntiles = (a.n + 15) / 16;
-    for (int tile = gw; tile < ntiles; tile += nw) {
-        const int b = tile * 16 + j;
+    const int last = a.n - 1;
+    int tile = gw;
+    int b = tile * 16 + j;
+    int2 p = a.xy[min(b, last)];
+    LatentFetch tap;
+    latent_fetch(a.grid, p.x, p.y, g, tap);
+    float4 t = a.target[min(b, last)];
+    int bn = b + 16 * nw;
+    int2 pn = a.xy[min(bn, last)];
+    // Wait for every load of the prologue (weights, biases, the first tile's
+    // inputs) here: the loop head then waits only for what the previous
+    // iteration requested, not for its atomics.
+    __builtin_amdgcn_s_waitcnt(0);
+    for (; tile < ntiles; tile += nw, b = bn, bn += 16 * nw) {
         const bool valid = b < a.n;
-        const int2 p = valid ? a.xy[b] : make_int2(0, 0);
-        LatentFetch tap;
-        latent_fetch(a.grid, p.x, p.y, g, tap);
         f4 X = latent_combine<P>(tap);
         if (!valid) X = zero;
         f4 z1[4], z2[4];
@@ -320,7 +349,6 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
         // loss and dY (lanes 0..15 hold the 4 channels of their sample)
         f4 dy = zero;
         if (g == 0 && valid) {
-            const float4 t = a.target[b];
             const float e0 = y[0] - t.x, e1 = y[1] - t.y, e2 = y[2] - t.z, e3 = y[3] - t.w;
             loss = __builtin_fmaf(e0, e0, __builtin_fmaf(e1, e1, __builtin_fmaf(e2, e2, __builtin_fmaf(e3, e3, loss))));
             dy[0] = e0 * a.gscale;
@@ -355,19 +383,38 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
         u16x8 dz1b[2];
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) dz1b[kc] = pack8<P>(dz1[2 * kc], dz1[2 * kc + 1]);
-        // dX = W1 dZ1: this lane's features, scattered to the latent corners
+        // dX = W1 dZ1: this lane's features of its sample (level g/2,
+        // channels 4(g%2)..+3), staged with the corner weights and cells
         f4 dx = Mfma<P>::k32(w1a[0], dz1b[0], zero);
         dx = Mfma<P>::k32(w1a[1], dz1b[1], dx);
-        if (a.glat && valid) {
-            int64_t* gl = a.glat + (g >= 2 ? (int64_t)a.l0 * a.l0 * 8 : 0) + 4 * (g & 1);
+        const int lv = g >> 1;
+        *reinterpret_cast<f4*>(&GS.dx[j][lv][4 * (g & 1)]) = dx;
+        if ((g & 1) == 0) {
+            *reinterpret_cast<f4*>(&GS.w[j][lv][0]) = f4{tap.w[0], tap.w[1], tap.w[2], tap.w[3]};
+            *reinterpret_cast<uint4*>(&GS.cell[j][lv][0]) = make_uint4(tap.cell[0], tap.cell[1], tap.cell[2], tap.cell[3]);
+        }
+        wave_lds_sync();
+
+        // next tile's inputs
+        latent_fetch(a.grid, pn.x, pn.y, g, tap);
+        t = a.target[min(bn, last)];
+        pn = a.xy[min(bn + 16 * nw, last)];
+
+        // this tile's latent gradients: instruction k, lane group s8 = lane/8
+        // adds channel lane%8 of (sample, level, corner) = combination 8k + s8
+        {
+            const int c = lane & 7, s8 = lane >> 3;
+            const int64_t lvl1 = (int64_t)a.l0 * a.l0 * 8;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const long long v = __float2ll_rn(tap.w[q] * dx[i] * kFxScale);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(gl + (int64_t)tap.cell[q] * 8 + i),
-                              (unsigned long long)v);
-                }
+            for (int k = 0; k < 16; ++k) {
+                const int combo = 8 * k + s8;
+                const int sm = combo >> 3, l = (combo >> 2) & 1, q = combo & 3;
+                const long long v = __float2ll_rn(GS.w[sm][l][q] * GS.dx[sm][l][c] * kFxScale);
+                atomicAdd(reinterpret_cast<unsigned long long*>(a.glat + (l ? lvl1 : 0) +
+                                                                (int64_t)GS.cell[sm][l][q] * 8 + c),
+                          (unsigned long long)v);
+            }
+            wave_lds_sync();
         }
 
         // weight gradients: batch contractions on MFMA over the 16 samples
@@ -478,34 +525,47 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
     if (lane == 0) a.loss_part[gw] = loss;
 }
 
-// Two-level fixed-order sum of the per-wave partials (deterministic):
-// level 1, block (x, y) sums waves [y*kSlice, (y+1)*kSlice) of parameters
-// x*256..; level 2 sums the slices.  Column mlp_count carries the loss.
-constexpr int kSlice = 32;
+// Fixed-order sum of the per-wave partials (deterministic), one pass: block
+// x sums columns [32x, 32x + 32) of the [waves][mlp_count] matrix (column
+// mlp_count: the per-wave losses).  Thread (c, r) adds rows r, r + 32, ...
+// of column c in order; the 32 row sums are then added as a fixed tree.
+constexpr int kRedCols = 32, kRedRows = 32;
 
-__global__ void k_reduce1(const float* __restrict__ partials, const float* __restrict__ loss_part,
-                          int waves, int mlp_count, float* __restrict__ slices)
+__global__ __launch_bounds__(kRedCols * kRedRows) void k_reduce(const float* __restrict__ partials,
+                                                                 const float* __restrict__ loss_part, int waves,
+                                                                 int mlp_count, float* __restrict__ grad_mlp,
+                                                                 float inv_count, float* __restrict__ loss_out)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int w0 = blockIdx.y * kSlice, w1 = min(waves, w0 + kSlice);
-    if (p > mlp_count) return;
+    __shared__ float part[kRedRows][kRedCols + 1];
+    const int c = threadIdx.x % kRedCols, r = threadIdx.x / kRedCols;
+    const int p = blockIdx.x * kRedCols + c;
+    // column p of the partials, or the losses for p == mlp_count
+    const float* col = p < mlp_count ? partials + p : loss_part;
+    const int64_t stride = p < mlp_count ? (int64_t)mlp_count : 1;
     float s = 0.f;
-    if (p < mlp_count)
-        for (int w = w0; w < w1; ++w) s += partials[(int64_t)w * mlp_count + p];
-    else
-        for (int w = w0; w < w1; ++w) s += loss_part[w];
-    slices[(int64_t)blockIdx.y * (mlp_count + 1) + p] = s;
-}
-
-__global__ void k_reduce2(const float* __restrict__ slices, int nslices, int mlp_count,
-                          float* __restrict__ grad_mlp, float inv_count, float* __restrict__ loss_out)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > mlp_count) return;
-    float s = 0.f;
-    for (int y = 0; y < nslices; ++y) s += slices[(int64_t)y * (mlp_count + 1) + p];
-    if (p < mlp_count) grad_mlp[p] = s;
-    else if (loss_out) loss_out[0] = s * inv_count;
+    if (p <= mlp_count) {
+        // eight rows requested at a time, added in row order
+        int w = r;
+        for (; w + 7 * kRedRows < waves; w += 8 * kRedRows) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = col[(int64_t)(w + u * kRedRows) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; w < waves; w += kRedRows) s += col[(int64_t)w * stride];
+    }
+    part[r][c] = s;
+    __syncthreads();
+#pragma unroll
+    for (int h = kRedRows / 2; h > 0; h >>= 1) {
+        if (r < h) part[r][c] += part[r + h][c];
+        __syncthreads();
+    }
+    if (r == 0) {
+        if (p < mlp_count) grad_mlp[p] = part[0][c];
+        else if (p == mlp_count && loss_out) loss_out[0] = part[0][c] * inv_count;
+    }
 }
 
 struct AdamArgs {
@@ -634,37 +694,34 @@ int train_waves(int n)
     return waves < kTrainWaves ? kTrainWaves : waves;
 }
 
-// Scratch of one loss/gradient pass: per-wave partial sums [waves][mlp_count],
-// per-wave losses [waves] and the reduction slices [waves / kSlice][mlp_count
-// + 1].  Every entry a pass reads is written by the same pass first.
+// Scratch of one loss/gradient pass: per-wave partial sums [waves][mlp_count]
+// and per-wave losses [waves].  Every entry a pass reads is written by the
+// same pass first.
 struct PassScratch {
     float* partials;
     float* loss_part;
-    float* slices;
 };
 
 hipError_t ensure_batch(ctf_decoder d, int32_t n)
 {
     if (n <= d->cap_batch) return hipSuccess;
-    for (void* p : {(void*)d->xy, (void*)d->target, (void*)d->partials, (void*)d->loss_part, (void*)d->slices})
+    for (void* p : {(void*)d->xy, (void*)d->target, (void*)d->partials, (void*)d->loss_part})
         if (p) (void)hipFree(p);
     d->xy = nullptr;
     d->target = nullptr;
     d->partials = nullptr;
     d->loss_part = nullptr;
-    d->slices = nullptr;
     d->cap_batch = 0;
     const int waves = train_waves(n);
     hipError_t e = hipMalloc(&d->xy, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc(&d->target, (size_t)n * 16);
     if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)waves * d->lay.mlp_count * 4);
     if (e == hipSuccess) e = hipMalloc(&d->loss_part, (size_t)waves * 4);
-    if (e == hipSuccess) e = hipMalloc(&d->slices, (size_t)((waves + 31) / 32) * (d->lay.mlp_count + 1) * 4);
     if (e == hipSuccess) d->cap_batch = n;
     return e;
 }
 
-PassScratch batch_scratch(ctf_decoder d) { return PassScratch{d->partials, d->loss_part, d->slices}; }
+PassScratch batch_scratch(ctf_decoder d) { return PassScratch{d->partials, d->loss_part}; }
 
 template <int P, bool UPDATE>
 hipError_t launch_adam(ctf_decoder d, float lr, hipStream_t s)
@@ -734,13 +791,9 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
     a.mlp_count = (int)L.mlp_count;
     const int waves = train_waves(n);
     hipLaunchKernelGGL((k_train<P>), dim3(waves / kTrainWaves), dim3(64 * kTrainWaves), 0, s, a);
-    const int rb = 256;
-    const int nsl = (waves + kSlice - 1) / kSlice;
-    const unsigned gx = (unsigned)((L.mlp_count + 1 + rb - 1) / rb);
-    hipLaunchKernelGGL(k_reduce1, dim3(gx, (unsigned)nsl), dim3(rb), 0, s, sc.partials, sc.loss_part, waves,
-                       (int)L.mlp_count, sc.slices);
-    hipLaunchKernelGGL(k_reduce2, dim3(gx), dim3(rb), 0, s, sc.slices, nsl, (int)L.mlp_count,
-                       grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
+    const unsigned gx = (unsigned)((L.mlp_count + 1 + kRedCols - 1) / kRedCols);
+    hipLaunchKernelGGL(k_reduce, dim3(gx), dim3(kRedCols * kRedRows), 0, s, sc.partials, sc.loss_part, waves,
+                       (int)L.mlp_count, grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
     if (latent_to_grad) hipLaunchKernelGGL(k_fx_to_float, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0, grad);
     return hipGetLastError();
 }
@@ -751,7 +804,7 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
 // Scratch of the allocation-free loss/gradient call.  One fixed array per
 // device (the code object's own copy), sized for CTF_NOALLOC_MAX_SAMPLES
 // samples of a decoder with hidden width <= 64: the per-wave partial sums,
-// per-wave losses and reduction slices of one pass (PassScratch).  Host code
+// and per-wave losses of one pass (PassScratch).  Host code
 // never passes `scratch` itself to a kernel: its device address is looked up
 // once per device at context creation (ctf_create) and kept in
 // g_scratch_dev.  Calls on one device share the array.
@@ -759,9 +812,8 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
 
 constexpr int kNoAllocWaves = 256;   // train_waves(CTF_NOALLOC_MAX_SAMPLES)
 constexpr int kNoAllocMlp = 16 * kHid + kHid + kHid * kHid + kHid + kHid * 4 + 4;
-constexpr int kNoAllocSlices = (kNoAllocWaves + kSlice - 1) / kSlice;
 constexpr size_t kNoAllocPartials = (size_t)kNoAllocWaves * kNoAllocMlp;
-constexpr size_t kNoAllocFloats = kNoAllocPartials + kNoAllocWaves + (size_t)kNoAllocSlices * (kNoAllocMlp + 1);
+constexpr size_t kNoAllocFloats = kNoAllocPartials + kNoAllocWaves;
 constexpr int kMaxScratchDevices = 64;
 
 static __device__ __align__(256) float scratch[kNoAllocFloats];
@@ -806,7 +858,7 @@ ctf_status ctf_decoder_destroy(ctf_decoder d)
     DeviceScope ds(d->ctx->device);
     for (void* p : {(void*)d->master, (void*)d->m, (void*)d->v, (void*)d->grad, (void*)d->glat_fx, (void*)d->lat_lp,
                     (void*)d->w_lp, (void*)d->bias_c, (void*)d->xy, (void*)d->target,
-                    (void*)d->partials, (void*)d->loss_part, (void*)d->slices, (void*)d->loss_tmp})
+                    (void*)d->partials, (void*)d->loss_part, (void*)d->loss_tmp})
         if (p) (void)hipFree(p);
     delete d;
     set_error("");
@@ -963,7 +1015,7 @@ ctf_status ctf_decoder_loss_grad_noalloc(ctf_decoder d, const int32_t* xy, const
     DeviceScope ds(d->ctx->device);
     if (ds.err != hipSuccess) return hip_fail(ds.err, "ctf_decoder_loss_grad_noalloc: set device");
     hipStream_t s = (hipStream_t)stream;
-    const PassScratch sc{base, base + kNoAllocPartials, base + kNoAllocPartials + kNoAllocWaves};
+    const PassScratch sc{base, base + kNoAllocPartials};
     hipError_t e = ensure_lp(d, precision, s);
     if (e == hipSuccess)
         e = precision == CTF_BF16 ? loss_grad_impl<CTF_BF16>(d, xy, target, n, loss, grad, true, true, sc, s)
