@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MLP_FLOP = 2 * (16 * 64 + 64 * 64 + 64 * 4)      # useful FLOP per decoded texel
-PROC_SLOTS_PER_TERM = 11                      # 7 full-rate VALU + v_sin_f32 (quarter rate: 4 slots)
+PROC_SLOTS_PER_TERM = 8                       # 4 full-rate VALU + v_sin_f32 (quarter rate: 4 slots)
 VALU_SLOT_PEAK = 256 * 4 * 32 * 2.4e9          # full-rate VALU lane-ops/s: 157.3 TFLOP/s fp32 / 2
 PEAK_FP16_TFLOPS = 2500.0                          # MI355X dense fp16/bf16 MFMA
 
@@ -301,10 +301,10 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
     ctex.close()
     cpu = None if args.no_cpu_baseline else cpu_oracle_procedural(sc, pqj, amp)
     b4 = res["bilinear4"]["gpixels_per_s"]
-    # ALU roofline of the texel evaluations: per term 7 full-rate VALU
-    # instructions (2 mul24, add3, and, cvt, mul, fma) and one v_sin_f32 at
-    # quarter rate = 11 lane slots; peak = 256 CUs x 4 SIMDs x 32 lanes x
-    # 2.4 GHz (the fp32 vector rate, one FMA per lane slot)
+    # ALU roofline of the texel evaluations: per term 4 full-rate VALU
+    # instructions (two FMAs for the exact phase, fract, the accumulating FMA)
+    # and one v_sin_f32 at quarter rate = 8 lane slots; peak = 256 CUs x 4
+    # SIMDs x 32 lanes x 2.4 GHz (the fp32 vector rate, one FMA per lane slot)
     slots_per_eval = 4 * 32 * PROC_SLOTS_PER_TERM
     for v in res.values():
         v["speedup_vs_bilinear4"] = v["gpixels_per_s"] / b4

@@ -149,7 +149,16 @@ ctf_status ctf_texture_create(ctf_context ctx, const ctf_texture_desc* d, ctf_te
             break;
         }
         const int K = d->n_terms;
-        std::vector<int32_t> host((size_t)4 * K * 4);
+        // the integer terms, then (W <= 4096) the float terms of the
+        // five-instruction form: residues p', q' in [-W/2, W/2), j' in [0, W),
+        // each divided by W (exact: W is a power of two)
+        const bool float_phase = d->width <= 4096;
+        std::vector<int32_t> host((size_t)4 * K * 4 * (float_phase ? 2 : 1));
+        const int64_t W = d->width;
+        auto centred = [&](int64_t v) {
+            int64_t r = ((v % W) + W) % W;
+            return r >= W / 2 ? r - W : r;
+        };
         for (int i = 0; i < 4 * K; ++i) {
             const int32_t p = d->pqj[3 * i], q = d->pqj[3 * i + 1], j = d->pqj[3 * i + 2];
             if (p <= -(1 << 23) || p >= (1 << 23) || q <= -(1 << 23) || q >= (1 << 23) || j < 0) {
@@ -163,6 +172,11 @@ ctf_status ctf_texture_create(ctf_context ctx, const ctf_texture_desc* d, ctf_te
             host[4 * i + 1] = q;
             host[4 * i + 2] = j;
             host[4 * i + 3] = bits;
+            if (float_phase) {
+                const float f[4] = {(float)centred(p) / (float)W, (float)centred(q) / (float)W,
+                                    (float)(((int64_t)j) % W) / (float)W, amp};
+                std::memcpy(&host[(size_t)4 * 4 * K + 4 * i], f, 16);
+            }
         }
         if (st != CTF_OK) break;
         hipError_t e = hipMalloc(&t->terms, host.size() * 4);
@@ -170,6 +184,7 @@ ctf_status ctf_texture_create(ctf_context ctx, const ctf_texture_desc* d, ctf_te
         if (e != hipSuccess) { st = hip_fail(e, "ctf_texture_create: terms"); break; }
         T.n_terms = K;
         T.terms = reinterpret_cast<const int4*>(t->terms);
+        T.fterms = float_phase ? reinterpret_cast<const float4*>(t->terms) + (size_t)4 * K : nullptr;
         break;
     }
     case CTF_TEX_AFFINE:

@@ -352,6 +352,9 @@ struct DevTexture {
     float inv_w;
     int n_terms;
     const int4* __restrict__ terms;   // [4][K] = (p, q, j, bits of amp)
+    // [4][K] = (p'/W, q'/W, j'/W, amp) with p', q' the residues of p, q mod W
+    // in [-W/2, W/2) and j' = j mod W; null when W > 4096
+    const float4* __restrict__ fterms;
     float affine[4][3];
     float constant[4];
     const float4* __restrict__ table; // [height][width]
@@ -371,6 +374,45 @@ typedef const __attribute__((address_space(4))) TermVec* ConstTerms;
 __device__ __forceinline__ ConstTerms const_terms(const int4* global_terms)
 {
     return (ConstTerms)global_terms;
+}
+
+typedef float FTermVec __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) FTermVec* ConstFTerms;
+
+__device__ __forceinline__ ConstFTerms const_fterms(const float4* global_terms)
+{
+    return (ConstFTerms)global_terms;
+}
+
+// The same channel from the float terms: v = p' x + q' y + j' is an integer
+// with |v| < W^2 <= 2^24, so both fused products and sums below are exact
+// and fract(v / W) is exactly (v mod W) / W, the argument the integer form
+// passes to the sine: the results are bit-identical to sinusoid_channel, in
+// five instructions per term instead of eight.
+template <class TermPtr>
+__device__ __forceinline__ float sinusoid_channel_f(TermPtr tc, int K, float xf, float yf)
+{
+    float acc = 0.0f;
+    // eight terms per iteration: their loads are issued together (one wait)
+    int k = 0;
+    for (; k + 8 <= K; k += 8) {
+        decltype(tc[0] + 0) t8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t8[u] = tc[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float ph = __builtin_fmaf(t8[u].x, xf, __builtin_fmaf(t8[u].y, yf, t8[u].z));
+            const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ph));
+            acc = __builtin_fmaf(t8[u].w, sn, acc);
+        }
+    }
+    for (; k < K; ++k) {
+        const auto tk = tc[k];
+        const float ph = __builtin_fmaf(tk.x, xf, __builtin_fmaf(tk.y, yf, tk.z));
+        const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ph));
+        acc = __builtin_fmaf(tk.w, sn, acc);
+    }
+    return __builtin_fmaf(0.5f, acc, 0.5f);
 }
 
 template <class TermPtr>
@@ -393,11 +435,20 @@ __device__ __forceinline__ float4 texel_eval(const DevTexture& T, int x, int y)
     if constexpr (KIND == CTF_TEX_SINUSOIDS) {
         const int xm = x & (int)T.wmask, ym = y & (int)T.wmask;
         const int K = T.n_terms;
-        const ConstTerms tc = const_terms(T.terms);
-        r.x = sinusoid_channel(tc + 0 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.y = sinusoid_channel(tc + 1 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.z = sinusoid_channel(tc + 2 * K, K, T.wmask, T.inv_w, xm, ym);
-        r.w = sinusoid_channel(tc + 3 * K, K, T.wmask, T.inv_w, xm, ym);
+        if (T.fterms) {
+            const ConstFTerms tc = const_fterms(T.fterms);
+            const float xf = (float)xm, yf = (float)ym;
+            r.x = sinusoid_channel_f(tc + 0 * K, K, xf, yf);
+            r.y = sinusoid_channel_f(tc + 1 * K, K, xf, yf);
+            r.z = sinusoid_channel_f(tc + 2 * K, K, xf, yf);
+            r.w = sinusoid_channel_f(tc + 3 * K, K, xf, yf);
+        } else {
+            const ConstTerms tc = const_terms(T.terms);
+            r.x = sinusoid_channel(tc + 0 * K, K, T.wmask, T.inv_w, xm, ym);
+            r.y = sinusoid_channel(tc + 1 * K, K, T.wmask, T.inv_w, xm, ym);
+            r.z = sinusoid_channel(tc + 2 * K, K, T.wmask, T.inv_w, xm, ym);
+            r.w = sinusoid_channel(tc + 3 * K, K, T.wmask, T.inv_w, xm, ym);
+        }
     } else if constexpr (KIND == CTF_TEX_AFFINE) {
         const float fx = (float)x, fy = (float)y;
         r.x = __builtin_fmaf(T.affine[0][2], fy, __builtin_fmaf(T.affine[0][1], fx, T.affine[0][0]));
@@ -410,6 +461,45 @@ __device__ __forceinline__ float4 texel_eval(const DevTexture& T, int x, int y)
         r = T.table[(size_t)(y & (int)T.hmask) * T.width + (x & (int)T.wmask)];
     }
     return r;
+}
+
+// Terms of a sinusoid texture staged in a workgroup's LDS: [4][K + 1] entries
+// (each channel's row padded by one entry, so that lanes reading the same
+// term of different channels hit different banks), the float terms when the
+// texture has them.  Textures with more terms are not staged.
+constexpr int kLdsTerms = 64;
+constexpr int kLdsTermEntries = 4 * (kLdsTerms + 1);
+
+// Every thread of the workgroup calls this (it synchronises the workgroup).
+__device__ inline bool stage_terms(const DevTexture& T, int4* terms_lds)
+{
+    if (T.kind != CTF_TEX_SINUSOIDS || T.n_terms > kLdsTerms) return false;
+    const int4* src = T.fterms ? reinterpret_cast<const int4*>(T.fterms) : T.terms;
+    for (int i = threadIdx.x; i < 4 * T.n_terms; i += blockDim.x) terms_lds[i + i / T.n_terms] = src[i];
+    __syncthreads();
+    return true;
+}
+
+// A texel from staged float terms (every lane reads the same entry, a
+// broadcast; the operands are then all vector registers, one instruction
+// fewer per term than with terms in scalar registers), else the texture's
+// own evaluation.  The same values either way.
+template <int KIND>
+__device__ __forceinline__ float4 texel_eval_staged(const DevTexture& T, const int4* terms_lds, bool lds_float, int x,
+                                                    int y)
+{
+    if constexpr (KIND == CTF_TEX_SINUSOIDS) {
+        if (lds_float) {
+            const int K = T.n_terms;
+            const float4* tl = reinterpret_cast<const float4*>(terms_lds);
+            const float xf = (float)(x & (int)T.wmask), yf = (float)(y & (int)T.wmask);
+            return make_float4(sinusoid_channel_f(tl + 0 * (K + 1), K, xf, yf),
+                               sinusoid_channel_f(tl + 1 * (K + 1), K, xf, yf),
+                               sinusoid_channel_f(tl + 2 * (K + 1), K, xf, yf),
+                               sinusoid_channel_f(tl + 3 * (K + 1), K, xf, yf));
+        }
+    }
+    return texel_eval<KIND>(T, x, y);
 }
 
 }  // namespace ctf

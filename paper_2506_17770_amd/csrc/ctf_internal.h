@@ -67,7 +67,7 @@ struct ctf_texture_s {
     ctf_context ctx;
     ctf_texture_desc desc;
     ctf::DevTexture dev;
-    void* terms = nullptr;      // device int4 [4][K]
+    void* terms = nullptr;      // device int4 [4][K], then float4 [4][K] (DevTexture::fterms)
     void* table = nullptr;      // device float4 [H][W]
     void* dec_buf = nullptr;    // device decoder weights (one allocation)
     ctf::DevDecoderWeights dec{};

@@ -230,7 +230,8 @@ __global__ void k_sample_sinusoid(DevTexture T, uint64_t seed, uint32_t step, in
     if (c == 0) xy[i] = p;
     const int xm = p.x & (int)T.wmask, ym = p.y & (int)T.wmask;
     target[4 * (int64_t)i + c] =
-        sinusoid_channel(const_terms(T.terms) + c * T.n_terms, T.n_terms, T.wmask, T.inv_w, xm, ym);
+        T.fterms ? sinusoid_channel_f(const_fterms(T.fterms) + c * T.n_terms, T.n_terms, (float)xm, (float)ym)
+                 : sinusoid_channel(const_terms(T.terms) + c * T.n_terms, T.n_terms, T.wmask, T.inv_w, xm, ym);
 }
 
 struct TrainArgs {

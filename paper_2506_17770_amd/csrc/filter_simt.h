@@ -99,34 +99,29 @@ __device__ __forceinline__ int list_find(const WaveLds<F>& L, int n, uint64_t ke
     return lo;
 }
 
-// Split-texel production reads the procedural terms from LDS (a lane's
-// channel varies across the wave, so they cannot come through the scalar
-// cache); up to this many terms per channel are staged.
-constexpr int kSplitTerms = 64;
-
 template <int METHOD, int TEX, bool STATS, int FILTER>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterArgs a, DevTexture T)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
     constexpr bool kCanSplit = (METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK) &&
                                TEX == CTF_TEX_SINUSOIDS;
+    constexpr bool kStage = TEX == CTF_TEX_SINUSOIDS;
     __shared__ WaveLds<F> lds_all[kWavesPerBlock];
-    // the four channels' terms, each channel's row padded by one entry so
-    // that the lanes of a split round, which read the same term of
-    // different channels, hit different LDS banks
-    __shared__ int4 terms_lds[kCanSplit ? 4 * (kSplitTerms + 1) : 1];
+    // the texture's terms (split rounds read them by channel; a lane's own
+    // texels read them by broadcast)
+    __shared__ int4 terms_lds[kStage ? kLdsTermEntries : 1];
     const int wid = wave_in_block();
     const int lane = lane_id();
     WaveLds<F>& L = lds_all[wid];
-    bool split_ok = false;
-    if constexpr (kCanSplit) {
-        split_ok = a.split == CTF_SPLIT_AUTO && T.n_terms <= kSplitTerms;
-        if (split_ok) {
-            for (int i = threadIdx.x; i < 4 * T.n_terms; i += blockDim.x)
-                terms_lds[i + i / T.n_terms] = T.terms[i];
-            __syncthreads();
-        }
+    bool staged = false, split_ok = false;
+    if constexpr (kStage) {
+        staged = stage_terms(T, terms_lds);
+        split_ok = kCanSplit && staged && a.split == CTF_SPLIT_AUTO;
     }
+    const bool lds_float = staged && T.fterms != nullptr;
+    auto texel = [&](int x, int y) __attribute__((always_inline)) -> float4 {
+        return texel_eval_staged<TEX>(T, terms_lds, lds_float, x, y);
+    };
     FrameCounters fc;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     for (TileWalk tw((int64_t)blockIdx.x * kWavesPerBlock + wid, nw, a.tiles_x); tw.tile < a.ntiles; tw.advance(nw)) {
@@ -157,15 +152,35 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         // ---- step 2: wave texel box over A
         int xmin = 0, ymin = 0, bbw = 0, bbh = 0;
         constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
-        if (kCollab || STATS) {
+        // Mask and List only need a 16x16 window that holds every footprint
+        // of A: try the one centred on a lane of A (lane 36 when it is in A)
+        // before reducing the exact box.  Bit positions are relative to the
+        // window's corner; the texels, their row-major order and every
+        // decision are the same as with the box's corner.
+        bool window = false;
+        if constexpr ((METHOD == CTF_LIST || METHOD == CTF_MASK) && !STATS) {
             if (nA > 0) {
+                constexpr int H = (16 - F) / 2;
+                const int rl = ((A >> 36) & 1ull) ? 36 : (int)__builtin_ctzll(A);
+                const int wx = __builtin_amdgcn_readlane(ox, rl) - H, wy = __builtin_amdgcn_readlane(oy, rl) - H;
+                const bool outside =
+                    inA && ((uint32_t)(ox - wx) > (uint32_t)(16 - F) || (uint32_t)(oy - wy) > (uint32_t)(16 - F));
+                if (ballot(outside) == 0) {
+                    window = true;
+                    xmin = wx;
+                    ymin = wy;
+                }
+            }
+        }
+        if (kCollab || STATS) {
+            if (nA > 0 && !window) {
                 xmin = wave_min(inA ? ox : INT32_MAX);
                 ymin = wave_min(inA ? oy : INT32_MAX);
                 bbw = wave_max(inA ? ox + F - 1 : INT32_MIN) - xmin + 1;
                 bbh = wave_max(inA ? oy + F - 1 : INT32_MIN) - ymin + 1;
             }
         }
-        const bool fits16 = nA > 0 && bbw <= 16 && bbh <= 16;
+        const bool fits16 = window || (nA > 0 && bbw <= 16 && bbh <= 16);
 
         // ---- 16x16 wave mask B (Mask Sampling; also the exact set when it fits)
         uint64_t B[4] = {0, 0, 0, 0};
@@ -261,10 +276,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         if constexpr (METHOD == CTF_BILINEAR4) {
             if (exact) {
                 if constexpr (F == 2) {
-                    const float4 v0 = texel_eval<TEX>(T, f.x0, f.y0);
-                    const float4 v1 = texel_eval<TEX>(T, f.x0 + 1, f.y0);
-                    const float4 v2 = texel_eval<TEX>(T, f.x0, f.y0 + 1);
-                    const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
+                    const float4 v0 = texel(f.x0, f.y0);
+                    const float4 v1 = texel(f.x0 + 1, f.y0);
+                    const float4 v2 = texel(f.x0, f.y0 + 1);
+                    const float4 v3 = texel(f.x0 + 1, f.y0 + 1);
                     res = bilerp(f.s, f.t, v0, v1, v2, v3);
                 } else {
                     float wx[4], wy[4];
@@ -272,8 +287,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                     taps32<FILTER>(f.t, wy);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const float4 r = row4(wx, texel_eval<TEX>(T, ox, oy + j), texel_eval<TEX>(T, ox + 1, oy + j),
-                                              texel_eval<TEX>(T, ox + 2, oy + j), texel_eval<TEX>(T, ox + 3, oy + j));
+                        const float4 r = row4(wx, texel(ox, oy + j), texel(ox + 1, oy + j),
+                                              texel(ox + 2, oy + j), texel(ox + 3, oy + j));
                         res = col_acc(wy[j], r, res, j == 0);
                     }
                 }
@@ -283,7 +298,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
             const bool pa = inA && P.produces, pd = draws && !inA;
             if (pa || pd) {
                 const int2 e = pa ? P.texel : pick;
-                const float4 v = texel_eval<TEX>(T, e.x, e.y);
+                const float4 v = texel(e.x, e.y);
                 if (pa) L.vals[P.slot] = v;
                 else res = v;
             }
@@ -321,8 +336,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                         const int2 e = item_xy(item);
                         if (c == 0) list_out(item, e);
                         float* v = reinterpret_cast<float*>(&L.vals[item]);
-                        v[c] = sinusoid_channel(terms_lds + c * (K + 1), K, T.wmask, T.inv_w, e.x & (int)T.wmask,
-                                                e.y & (int)T.wmask);
+                        const int xm = e.x & (int)T.wmask, ym = e.y & (int)T.wmask;
+                        v[c] = T.fterms ? sinusoid_channel_f(reinterpret_cast<const float4*>(terms_lds) + c * (K + 1),
+                                                             K, (float)xm, (float)ym)
+                                        : sinusoid_channel(terms_lds + c * (K + 1), K, T.wmask, T.inv_w, xm, ym);
                     }
                 }
             }
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                     list_out(item, e);
                 }
                 if (produce || draw_now) {
-                    const float4 v = texel_eval<TEX>(T, e.x, e.y);
+                    const float4 v = texel(e.x, e.y);
                     if (produce) L.vals[item] = v;
                     if (draw_now) res = v;
                 }
@@ -346,30 +363,32 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                 // ---- gather: item index of each footprint texel, then weight
                 wave_lds_sync();
                 if (exact) {
-                    // item index of tap (i, j)
-                    auto item_of = [&](int i, int j) -> int {
+                    // item index of the first tap of footprint row j; the
+                    // row's other taps are the next items (the set holds the
+                    // whole row, in row-major order for Mask and List)
+                    auto row_item = [&](int j) -> int {
                         if constexpr (METHOD == CTF_BOX) {
-                            return (ox + i - xmin) + (oy + j - ymin) * bbw;
+                            return (ox - xmin) + (oy + j - ymin) * bbw;
                         } else {
                             if (sorted) {
                                 const uint64_t key = ((uint64_t)(uint32_t)(oy + j - ymin) << 32) |
-                                                     (uint32_t)(ox + i - xmin);
+                                                     (uint32_t)(ox - xmin);
                                 return list_find<F>(L, n, key);
                             }
-                            return L.rank[16 * (oy + j - ymin) + (ox + i - xmin)];
+                            return L.rank[16 * (oy + j - ymin) + (ox - xmin)];
                         }
                     };
                     if constexpr (F == 2) {
-                        res = bilerp(f.s, f.t, L.vals[item_of(0, 0)], L.vals[item_of(1, 0)], L.vals[item_of(0, 1)],
-                                     L.vals[item_of(1, 1)]);
+                        const int i0 = row_item(0), i2 = row_item(1);
+                        res = bilerp(f.s, f.t, L.vals[i0], L.vals[i0 + 1], L.vals[i2], L.vals[i2 + 1]);
                     } else {
                         float wx[4], wy[4];
                         taps32<FILTER>(f.s, wx);
                         taps32<FILTER>(f.t, wy);
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const float4 r = row4(wx, L.vals[item_of(0, j)], L.vals[item_of(1, j)],
-                                                  L.vals[item_of(2, j)], L.vals[item_of(3, j)]);
+                            const int i0 = row_item(j);
+                            const float4 r = row4(wx, L.vals[i0], L.vals[i0 + 1], L.vals[i0 + 2], L.vals[i0 + 3]);
                             res = col_acc(wy[j], r, res, j == 0);
                         }
                     }

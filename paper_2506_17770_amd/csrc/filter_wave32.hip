@@ -286,10 +286,23 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
     __shared__ W32Lds<F> lds_all[kW32Waves];
+    __shared__ int4 terms_lds[TEX == CTF_TEX_SINUSOIDS && (METHOD == CTF_BILINEAR4 || METHOD == CTF_STF1)
+                                  ? kLdsTermEntries
+                                  : 1];
     const int wid = wave_in_block();
     const int lane = lane_id();
     const int h = lane >> 5, ll = lane & 31;
     W32Lds<F>& L = lds_all[wid];
+    // Terms from LDS for the 4-tap and one-tap kernels; the collaborative
+    // ones keep them in scalar registers (the LDS copy and the extra vector
+    // registers cost them occupancy: List 8x4 at 1080p 21.3 against 24.0
+    // Gpixels/s)
+    constexpr bool kStage = TEX == CTF_TEX_SINUSOIDS && (METHOD == CTF_BILINEAR4 || METHOD == CTF_STF1);
+    bool lds_float = false;
+    if constexpr (kStage) lds_float = stage_terms(T, terms_lds) && T.fterms != nullptr;
+    auto texel = [&](int x, int y) __attribute__((always_inline)) -> float4 {
+        return texel_eval_staged<TEX>(T, terms_lds, lds_float, x, y);
+    };
     FrameCounters fc;
     const int64_t npairs = (a.ntiles + 1) / 2;
     const int64_t nw = (int64_t)gridDim.x * kW32Waves;
@@ -468,10 +481,10 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
         if constexpr (METHOD == CTF_BILINEAR4) {
             if (exact) {
                 if constexpr (F == 2) {
-                    const float4 v0 = texel_eval<TEX>(T, f.x0, f.y0);
-                    const float4 v1 = texel_eval<TEX>(T, f.x0 + 1, f.y0);
-                    const float4 v2 = texel_eval<TEX>(T, f.x0, f.y0 + 1);
-                    const float4 v3 = texel_eval<TEX>(T, f.x0 + 1, f.y0 + 1);
+                    const float4 v0 = texel(f.x0, f.y0);
+                    const float4 v1 = texel(f.x0 + 1, f.y0);
+                    const float4 v2 = texel(f.x0, f.y0 + 1);
+                    const float4 v3 = texel(f.x0 + 1, f.y0 + 1);
                     res = bilerp(f.s, f.t, v0, v1, v2, v3);
                 } else {
                     float wx[4], wy[4];
@@ -479,8 +492,8 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                     taps32<FILTER>(f.t, wy);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const float4 r = row4(wx, texel_eval<TEX>(T, ox, oy + j), texel_eval<TEX>(T, ox + 1, oy + j),
-                                              texel_eval<TEX>(T, ox + 2, oy + j), texel_eval<TEX>(T, ox + 3, oy + j));
+                        const float4 r = row4(wx, texel(ox, oy + j), texel(ox + 1, oy + j),
+                                              texel(ox + 2, oy + j), texel(ox + 3, oy + j));
                         res = col_acc(wy[j], r, res, j == 0);
                     }
                 }
@@ -510,14 +523,14 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                     if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = make_int2(ex, ey);
                 }
                 if (produce || draw_now) {
-                    const float4 v = texel_eval<TEX>(T, ex, ey);
+                    const float4 v = texel(ex, ey);
                     if (produce) L.vals[h][item] = v;
                     if (draw_now) res = v;
                 }
             }
             if constexpr (FB && kCollab) {
                 // the fallback halves' planned texels, then Eq. 1
-                if (fbl && inA && P.produces) L.vals[h][P.slot] = texel_eval<TEX>(T, P.texel.x, P.texel.y);
+                if (fbl && inA && P.produces) L.vals[h][P.slot] = texel(P.texel.x, P.texel.y);
                 wave_lds_sync();
                 if (fbl && inA) res = fallback_color_w32<FILTER, F>(L, P, h, h ? nprod1 : nprod0, f, pick, xmin, ymin);
             }
