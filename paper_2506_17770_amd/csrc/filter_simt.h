@@ -124,7 +124,34 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
     };
     FrameCounters fc;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    for (TileWalk tw((int64_t)blockIdx.x * kWavesPerBlock + wid, nw, a.tiles_x); tw.tile < a.ntiles; tw.advance(nw)) {
+    // The inputs of the wave's next tile are loaded one tile ahead, the
+    // tile's output is stored at its end.  Both are unconditional (a lane off
+    // the screen loads pixel 0 and its coordinates are replaced by NaN when
+    // used; it repeats the store of lane 0, which is on the screen in every
+    // tile): the memory counters complete in order, and a load or store
+    // skipped on some path would make the wait for the next tile's inputs
+    // also wait for this tile's store.
+    auto load_px = [&](const TileWalk& t, float2& uv, float4& d) __attribute__((always_inline)) -> bool {
+        const int qx = t.tx * kTile + (lane & 7), qy = t.ty * kTile + (lane >> 3);
+        const bool ok = t.tile < a.ntiles && qx < a.sw && qy < a.sh;
+        const int64_t q = ok ? (int64_t)qy * a.sw + qx : 0;
+        uv = reinterpret_cast<const float2*>(a.uv)[q];
+        d = reinterpret_cast<const float4*>(a.duv)[q];
+        return ok;
+    };
+    TileWalk next((int64_t)blockIdx.x * kWavesPerBlock + wid, nw, a.tiles_x);
+    float2 uv_next;
+    float4 d_next;
+    bool ok_next = load_px(next, uv_next, d_next);
+    // wait for the first tile's inputs here, so that the loop head waits
+    // only for what the previous iteration requested
+    asm volatile("" ::"v"(uv_next.x), "v"(uv_next.y), "v"(d_next.x), "v"(d_next.y), "v"(d_next.z), "v"(d_next.w));
+    while (next.tile < a.ntiles) {
+        const TileWalk tw = next;
+        const float2 uv_cur = ok_next ? uv_next : make_float2(__builtin_nanf(""), 0.f);
+        const float4 d_cur = ok_next ? d_next : make_float4(0.f, 0.f, 0.f, 0.f);
+        next.advance(nw);
+        ok_next = load_px(next, uv_next, d_next);
         const int64_t tile = tw.tile;
         const int tx = tw.tx, ty = tw.ty;
         const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
@@ -132,16 +159,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         const int64_t pix = (int64_t)py * a.sw + px;
 
         // ---- step 1: footprint, participation (A = active and magnifying)
-        Footprint f;
-        {
-            float2 uv = make_float2(__builtin_nanf(""), 0.f);
-            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (in_screen) {
-                uv = reinterpret_cast<const float2*>(a.uv)[pix];
-                d = reinterpret_cast<const float4*>(a.duv)[pix];
-            }
-            f = footprint(uv.x, uv.y, d, (float)T.width, (float)T.height);
-        }
+        const Footprint f = footprint(uv_cur.x, uv_cur.y, d_cur, (float)T.width, (float)T.height);
         const int ox = f.x0 - O, oy = f.y0 - O;   // upper-left tap of the FxF footprint
         const bool inA = f.active && f.magnify;
         const uint64_t act = ballot(f.active);
@@ -397,11 +415,17 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         }
 
         // ---- outputs
-        if (in_screen) {
-            reinterpret_cast<float4*>(a.out)[pix] = res;
-            if (a.stf_xy) reinterpret_cast<int2*>(a.stf_xy)[pix] =
-                draws ? pick : make_int2(INT32_MIN, INT32_MIN);
+        {
+            // (selected per component: a select of two float4 lvalues
+            // would put both in memory)
+            auto lane0 = [&](float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)); };
+            const float4 o = make_float4(in_screen ? res.x : lane0(res.x), in_screen ? res.y : lane0(res.y),
+                                         in_screen ? res.z : lane0(res.z), in_screen ? res.w : lane0(res.w));
+            const int64_t pix0 = (int64_t)(ty * kTile) * a.sw + tx * kTile;
+            reinterpret_cast<float4*>(a.out)[in_screen ? pix : pix0] = o;
         }
+        if (in_screen && a.stf_xy)
+            reinterpret_cast<int2*>(a.stf_xy)[pix] = draws ? pick : make_int2(INT32_MIN, INT32_MIN);
         const int nstf = popc64(stfmask);
         int evals;
         if constexpr (METHOD == CTF_BILINEAR4) evals = F * F * popc64(act);
