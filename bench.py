@@ -279,13 +279,17 @@ def bench_procedural(ctx, ctf, cs, torch, args, stream):
                     ("mask_8x4", ctf.method(ctf.MASK, wave_shape=ctf.WAVE_8X4)),
                     ("mask_fbCplus_8x4", ctf.method(ctf.MASK, fallback=ctf.FB_CPLUS, wave_shape=ctf.WAVE_8X4))):
         fs = ctf.frame_stats_buffer()
-        ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs)
+        ts = ctf.tile_stats_buffer(1920, 1080, meth=m)
+        ctx.filter(uv, duv, tex, m, out=out, frame_stats=fs, tile_stats=ts)
         torch.cuda.synchronize()
         st = ctf.frame_stats_dict(fs)
+        rec = ts.cpu().numpy().view(ctf.TILE_STATS_DTYPE).reshape(-1)
+        used = rec["part"] != 0   # waves with at least one magnifying lane
         _, per = timed(lambda: ctx.filter(uv, duv, tex, m, out=out), stream, max(3, args.steps // 2), 2, torch)
         ms = float(np.mean(per))
         res[name] = {"gpixels_per_s": npx / (ms * 1e-3) / 1e9, "ms": ms,
                      "texel_evals_per_pixel": st["evals"] / npx,
+                     "unique_texels_per_wave": float(rec["unique"][used].mean()) if used.any() else 0.0,
                      "not_exact_fraction": st["stf"] / max(1, st["active"]),
                      "waves_failed": st["tiles_fail"], "waves_ok": st["tiles_ok"]}
     # the dedup machinery's own cost: the same frame on a constant texture,
@@ -562,7 +566,9 @@ def summary_line(res, details_path):
         line["procedural_1080p"] = {
             "roofline_frac_list": round(p["roofline"]["frac"], 4),
             "methods": {k: {"gpx": round(v["gpixels_per_s"], 2), "x_b4": round(v["speedup_vs_bilinear4"], 2),
-                            "evals_px": round(v["texel_evals_per_pixel"], 3), "alu_frac": round(v["alu_frac"], 3)}
+                            "evals_px": round(v["texel_evals_per_pixel"], 3), "alu_frac": round(v["alu_frac"], 3),
+                            "uniq_wave": round(v["unique_texels_per_wave"], 1),
+                            "fb_frac": round(v["not_exact_fraction"], 3)}
                         for k, v in p["methods"].items()},
             "overhead_us_per_mpixel": {k: round(v["us_per_mpixel"], 2)
                                        for k, v in p["constant_texture_overhead"].items()}}

@@ -38,7 +38,7 @@ def test_summary_line_fits_the_record_and_ends_with_the_metric(tmp_path):
     sys.path.insert(0, ROOT)
     import bench
     meth = {"gpixels_per_s": 23.123456, "ms": 0.0899, "texel_evals_per_pixel": 0.70533,
-            "not_exact_fraction": 0.357, "waves_failed": 2100, "waves_ok": 20835,
+            "not_exact_fraction": 0.357, "waves_failed": 2100, "waves_ok": 20835, "unique_texels_per_wave": 46.123,
             "speedup_vs_bilinear4": 3.4257, "alu_frac": 0.29476}
     names = ["bilinear4", "stf1", "list", "box4x4", "box6x6", "mask", "mask_fbC", "mask_fbCplus", "list_k2",
              "list_no_split", "mask_no_split", "bilinear4_8x4", "list_8x4", "box4x4_8x4", "mask_8x4",

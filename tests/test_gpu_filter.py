@@ -130,6 +130,32 @@ def test_texel_eval_matches_float64(G):
     tex.close()
 
 
+@pytest.mark.parametrize("W", [64, 4096, 8192])
+def test_texel_eval_extreme_frequencies(G, W):
+    """Frequencies and phases far outside [0, W) (up to the API's 2^23): the
+    float phase form (W <= 4096, residues prepared at texture creation) and
+    the integer form (W > 4096) both reduce them exactly; a wrong residue
+    would give errors of order 1."""
+    ctf, ctx, torch = G
+    rng = np.random.default_rng(W)
+    K = 16
+    pqj = np.stack([rng.integers(-(1 << 23) + 1, 1 << 23, (4, K)), rng.integers(-(1 << 23) + 1, 1 << 23, (4, K)),
+                    rng.integers(0, 1 << 31, (4, K))], axis=-1).astype(np.int32)
+    pqj[0, 0] = (W // 2, -W // 2, W - 1)          # the residues' extremes
+    pqj[0, 1] = (-W // 2 - 1, W // 2 - 1, 3 * W)
+    a = rng.uniform(0.5, 1.5, (4, K))
+    amp = (a / a.sum(axis=1, keepdims=True)).astype(np.float32)
+    tex = ctx.sinusoid_texture(W, pqj, amp)
+    xy = rng.integers(-(2**24), 2**24, (50000, 2)).astype(np.int32)
+    xy[:4] = [(W - 1, W - 1), (0, 0), (-1, -1), (2**24 - 1, -(2**24))]
+    got = tex.eval(torch.from_numpy(xy).cuda()).cpu().numpy()
+    want = O.sinusoid_texture(W, pqj, amp).eval(xy)
+    err = np.abs(got - want).max()
+    print(f"texel error W={W}: {err:.3g}")
+    assert err < 1e-6, err
+    tex.close()
+
+
 def test_affine_and_constant_textures(G, c0):
     ctf, ctx, _ = G
     sc = c0[0]
