@@ -250,6 +250,8 @@ struct TrainArgs {
 };
 
 constexpr int kTrainWaves = 4;
+// MLP parameters of a decoder with hidden width <= 64 (16H + H + H^2 + H + 4H + 4)
+constexpr int kMlpMax = 16 * kHid + kHid + kHid * kHid + kHid + kHid * 4 + 4;
 
 // 16x16 block in C layout (lane: column l%16, rows 4g..4g+3) -> the
 // transposed operand (lane: row/column l%16 of the units, k = columns
@@ -284,6 +286,8 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
 {
     __shared__ uint16_t lds[kTrainWaves][18][256];
     __shared__ GradStage gst[kTrainWaves];
+    __shared__ float red[kTrainWaves][kMlpMax];   // per-wave MLP gradient partials
+    __shared__ float red_loss[kTrainWaves];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
@@ -479,9 +483,10 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) loss += __shfl_xor(loss, o, 64);
 
-    // write this wave's partial sums in the flat order (relative to W1)
+    // this wave's partial sums in the flat order (relative to W1), into the
+    // workgroup's LDS rows; the workgroup then writes their fixed-order sum
     const int H = a.hidden;
-    float* out = a.partials + (int64_t)gw * a.mlp_count;
+    float* out = red[wid];
     const int oW1 = 0, ob1 = 16 * H, oW2 = ob1 + H, ob2 = oW2 + H * H, oW3 = ob2 + H, ob3 = oW3 + 4 * H;
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb)
@@ -523,7 +528,21 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) out[ob3 + r] = ab3[r];
     }
-    if (lane == 0) a.loss_part[gw] = loss;
+    if (lane == 0) red_loss[wid] = loss;
+    __syncthreads();
+    float* bout = a.partials + (int64_t)blockIdx.x * a.mlp_count;
+    for (int i = threadIdx.x; i < a.mlp_count; i += blockDim.x) {
+        float v = red[0][i];
+#pragma unroll
+        for (int w = 1; w < kTrainWaves; ++w) v += red[w][i];
+        bout[i] = v;
+    }
+    if (threadIdx.x == 0) {
+        float v = red_loss[0];
+#pragma unroll
+        for (int w = 1; w < kTrainWaves; ++w) v += red_loss[w];
+        a.loss_part[blockIdx.x] = v;
+    }
 }
 
 // Fixed-order sum of the per-wave partials (deterministic), one pass: block
@@ -793,8 +812,9 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
     const int waves = train_waves(n);
     hipLaunchKernelGGL((k_train<P>), dim3(waves / kTrainWaves), dim3(64 * kTrainWaves), 0, s, a);
     const unsigned gx = (unsigned)((L.mlp_count + 1 + kRedCols - 1) / kRedCols);
-    hipLaunchKernelGGL(k_reduce, dim3(gx), dim3(kRedCols * kRedRows), 0, s, sc.partials, sc.loss_part, waves,
-                       (int)L.mlp_count, grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
+    // one partial row per workgroup (the sum of its waves' rows)
+    hipLaunchKernelGGL(k_reduce, dim3(gx), dim3(kRedCols * kRedRows), 0, s, sc.partials, sc.loss_part,
+                       waves / kTrainWaves, (int)L.mlp_count, grad + L.mlp0, 1.0f / (4.0f * (float)n), loss);
     if (latent_to_grad) hipLaunchKernelGGL(k_fx_to_float, dim3(fb), dim3(256), 0, s, d->glat_fx, L.mlp0, grad);
     return hipGetLastError();
 }
