@@ -317,7 +317,7 @@ ctf_status ctf_decoder_loss_grad(ctf_decoder dec, const int32_t *xy, const float
  * loss and gradient are bitwise equal to that call's); the caller still
  * provides xy, target, loss and grad (device memory).
  * Scratch: a fixed array the library holds on each device from the first
- * ctf_create on that device until the process ends (5.6 MB: per-wave
+ * ctf_create on that device until the process ends (1.4 MB: per-workgroup
  * partial sums of one pass over at most CTF_NOALLOC_MAX_SAMPLES samples of a
  * decoder with hidden width <= 64), instead of the decoder's batch buffers.
  * Every call on a device uses that device's one array and each pass writes

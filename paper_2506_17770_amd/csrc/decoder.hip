@@ -7,9 +7,10 @@
 //   k_train    forward + backward on MFMA for 16-sample tiles (operands in
 //              bf16 or fp16, float32 accumulation), latent gradients
 //              scattered as 64-bit fixed-point atomics (order independent,
-//              so training is bitwise reproducible), per-wave partial sums of the
-//              MLP weight gradients (batch reductions on MFMA after an LDS
-//              transpose of each 16x16 block);
+//              so training is bitwise reproducible), per-workgroup partial
+//              sums of the MLP weight gradients (batch reductions on MFMA
+//              after an LDS transpose of each 16x16 block, the waves' sums
+//              added in LDS in a fixed order);
 //   k_reduce   fixed-order sum of the partials (deterministic) and the loss;
 //   k_adam     Adam on the master copy, rewriting the low-precision latent
 //              copy and the packed MFMA weight blocks.
@@ -244,8 +245,8 @@ struct TrainArgs {
     int n;                    // samples
     float gscale;             // 2 / (4 n)
     int64_t* glat;            // latent gradient, fixed point (flat, atomics)
-    float* partials;          // [waves][mlp_count]
-    float* loss_part;         // [waves]
+    float* partials;          // [workgroups][mlp_count]
+    float* loss_part;         // [workgroups]
     int mlp_count;
 };
 
@@ -545,9 +546,9 @@ __global__ __launch_bounds__(64 * kTrainWaves, 1) void k_train(TrainArgs a)
     }
 }
 
-// Fixed-order sum of the per-wave partials (deterministic), one pass: block
-// x sums columns [32x, 32x + 32) of the [waves][mlp_count] matrix (column
-// mlp_count: the per-wave losses).  Thread (c, r) adds rows r, r + 32, ...
+// Fixed-order sum of the per-workgroup partials (deterministic), one pass: block
+// x sums columns [32x, 32x + 32) of the [rows][mlp_count] matrix (column
+// mlp_count: the per-workgroup losses).  Thread (c, r) adds rows r, r + 32, ...
 // of column c in order; the 32 row sums are then added as a fixed tree.
 constexpr int kRedCols = 32, kRedRows = 32;
 
@@ -714,8 +715,9 @@ int train_waves(int n)
     return waves < kTrainWaves ? kTrainWaves : waves;
 }
 
-// Scratch of one loss/gradient pass: per-wave partial sums [waves][mlp_count]
-// and per-wave losses [waves].  Every entry a pass reads is written by the
+// Scratch of one loss/gradient pass: per-workgroup partial sums
+// [waves / kTrainWaves][mlp_count] and per-workgroup losses.  Every entry a
+// pass reads is written by the
 // same pass first.
 struct PassScratch {
     float* partials;
@@ -735,8 +737,8 @@ hipError_t ensure_batch(ctf_decoder d, int32_t n)
     const int waves = train_waves(n);
     hipError_t e = hipMalloc(&d->xy, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc(&d->target, (size_t)n * 16);
-    if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)waves * d->lay.mlp_count * 4);
-    if (e == hipSuccess) e = hipMalloc(&d->loss_part, (size_t)waves * 4);
+    if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)(waves / kTrainWaves) * d->lay.mlp_count * 4);
+    if (e == hipSuccess) e = hipMalloc(&d->loss_part, (size_t)(waves / kTrainWaves) * 4);
     if (e == hipSuccess) d->cap_batch = n;
     return e;
 }
@@ -824,8 +826,8 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
 // ---------------------------------------------------------------------------
 // Scratch of the allocation-free loss/gradient call.  One fixed array per
 // device (the code object's own copy), sized for CTF_NOALLOC_MAX_SAMPLES
-// samples of a decoder with hidden width <= 64: the per-wave partial sums,
-// and per-wave losses of one pass (PassScratch).  Host code
+// samples of a decoder with hidden width <= 64: the per-workgroup partial
+// sums and losses of one pass (PassScratch).  Host code
 // never passes `scratch` itself to a kernel: its device address is looked up
 // once per device at context creation (ctf_create) and kept in
 // g_scratch_dev.  Calls on one device share the array.
@@ -833,8 +835,9 @@ hipError_t loss_grad_impl(ctf_decoder d, const int32_t* xy, const float* target,
 
 constexpr int kNoAllocWaves = 256;   // train_waves(CTF_NOALLOC_MAX_SAMPLES)
 constexpr int kNoAllocMlp = 16 * kHid + kHid + kHid * kHid + kHid + kHid * 4 + 4;
-constexpr size_t kNoAllocPartials = (size_t)kNoAllocWaves * kNoAllocMlp;
-constexpr size_t kNoAllocFloats = kNoAllocPartials + kNoAllocWaves;
+constexpr int kNoAllocGroups = kNoAllocWaves / kTrainWaves;
+constexpr size_t kNoAllocPartials = (size_t)kNoAllocGroups * kNoAllocMlp;
+constexpr size_t kNoAllocFloats = kNoAllocPartials + kNoAllocGroups;
 constexpr int kMaxScratchDevices = 64;
 
 static __device__ __align__(256) float scratch[kNoAllocFloats];
