@@ -314,8 +314,23 @@ struct TileWalk {
 
 // Frame totals of one wave over all its tiles, added to the frame record
 // once at the end (one set of atomics per wave).
+// Per-wave sums of the frame counters, added to the frame's 64-bit counters
+// at the end of the kernel.  32-bit (half the scalar registers): a tile adds
+// at most 2^13 to any of them, and every launch gives each wave at most
+// kMaxWaveTileVisits tile visits (layers counted once each), so none can
+// overflow.
+constexpr int64_t kMaxWaveTileVisits = int64_t(1) << 18;
+
+// Workgroups of `waves_per_block` waves a launch needs so that no wave visits
+// more than kMaxWaveTileVisits tiles.
+inline int64_t counter_min_blocks(int64_t tile_visits, int waves_per_block)
+{
+    const int64_t waves = (tile_visits + kMaxWaveTileVisits - 1) / kMaxWaveTileVisits;
+    return (waves + waves_per_block - 1) / waves_per_block;
+}
+
 struct FrameCounters {
-    uint64_t evals = 0, active = 0, stf = 0, minify = 0, tiles = 0, rows = 0, ok = 0, fail = 0;
+    uint32_t evals = 0, active = 0, stf = 0, minify = 0, tiles = 0, rows = 0, ok = 0, fail = 0;
     __device__ __forceinline__ void add(int e, int act, int nstf, int mini, int rws, bool okk, bool fl)
     {
         evals += e;

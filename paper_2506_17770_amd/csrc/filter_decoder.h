@@ -317,7 +317,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
             reinterpret_cast<float4*>(a.out)[pix] = res;
             if (a.stf_xy) reinterpret_cast<int2*>(a.stf_xy)[pix] = make_int2(INT32_MIN, INT32_MIN);
         }
-        if (lane == 0 && a.tile_stats)
+        if (STATS && lane == 0 && a.tile_stats)
             write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, 4 * R, success,
                              cap_ok, count_ok, nA);
         if (act) fc.add(4 * R, popc64(act), nstf, popc64(act & ~A), 4 * ((R + 15) & ~15), false, false);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
                         ey = ymin + (int)(key >> 32);
                     }
                     L.rows[i] = make_int2(ex, ey);
-                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+                    if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
                 }
             } else {
                 // set bit t of B with rank r: row r, and rank[t] = r (h^-1)
@@ -378,7 +378,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
                         const int2 c = make_int2(xmin + (t & 15), ymin + (t >> 4));
                         L.rank[t] = (uint8_t)r;
                         L.rows[r] = c;
-                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
+                        if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = c;
                     }
                     base += popc64(B[w]);
                 }
@@ -454,7 +454,7 @@ __device__ __forceinline__ void dec_tile(const FilterArgs& a, const InferGrid& G
         }
     }
     if (in_screen) reinterpret_cast<float4*>(a.out)[pix] = res;
-    if (lane == 0 && a.tile_stats)
+    if (STATS && lane == 0 && a.tile_stats)
         write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, R, success, cap_ok,
                          count_ok, nA);
     if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), (R + 15) & ~15, kCollab && success,
@@ -626,7 +626,6 @@ struct BatchLds {
 };
 
 struct Pending {
-    int64_t tile;
     int tx, ty;
     int base;                   // first row of the tile in the batch
 };
@@ -788,7 +787,7 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
                         ey = ymin + (int)(key >> 32);
                     }
                     dst[i] = make_int2(ex, ey);
-                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
+                    if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + i] = make_int2(ex, ey);
                 }
             } else {
                 // bit `lane` of word w is position 64 w + lane of the window:
@@ -801,7 +800,7 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
                         const int r = first + mbcnt(B[w]);
                         rank[64 * w + lane] = (uint8_t)r;
                         dst[r] = make_int2(cx, cy);
-                        if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = make_int2(cx, cy);
+                        if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + r] = make_int2(cx, cy);
                     }
                     first += popc64(B[w]);
                     cy += 4;
@@ -831,7 +830,7 @@ __device__ __forceinline__ int plan_tile(const FilterArgs& a, BatchLds& BL, int 
     ls.misc = (uint32_t)((ns + mbcnt(stfmask)) & 0xff) | (exact ? 1u << 8 : 0u) | (draws ? 1u << 9 : 0u) |
               (in_screen ? 1u << 10 : 0u);
     BL.st[slot][lane] = ls;
-    if (lane == 0 && a.tile_stats)
+    if (STATS && lane == 0 && a.tile_stats)
         write_tile_stats(a, tile, act, A, stfmask, fits16, B, xmin, ymin, bbw, bbh, n, unique, R, success, cap_ok,
                          count_ok, nA);
     if (act) fc.add(R, popc64(act), nstf, popc64(act & ~A), 0, kCollab && success, kCollab && nA && !success);
@@ -883,7 +882,7 @@ __device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, B
     wave_lds_sync();
     if (bt.npend >= 1) gather_tile<METHOD>(a, BL, 0, bt.p0);
     if (bt.npend == 2) gather_tile<METHOD>(a, BL, 1, bt.p1);
-    fc.rows += (uint64_t)((bt.rows + 15) & ~15);
+    fc.rows += (uint32_t)((bt.rows + 15) & ~15);
     bt.npend = 0;
     bt.rows = 0;
     wave_lds_sync();
@@ -910,7 +909,6 @@ __device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Bat
     }
     wave_lds_sync();   // the next plan rewrites the keys
     Pending& pd = bt.npend ? bt.p1 : bt.p0;
-    pd.tile = cur.tile;
     pd.tx = cur.tx;
     pd.ty = cur.ty;
     pd.base = bt.rows;
@@ -965,12 +963,13 @@ inline int device_cus()
 // Persistent grid: as many workgroups as fit on the device at once (from the
 // kernel's register and LDS use), a multiple of the 8 XCDs.
 template <typename K>
-int64_t resident_blocks(K kernel, int threads, int64_t work_blocks)
+int64_t resident_blocks(K kernel, int threads, int64_t work_blocks, int64_t min_blocks)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int64_t blocks = (int64_t)device_cus() * per_cu;
+    if (blocks < min_blocks) blocks = min_blocks;
     if (blocks > work_blocks) blocks = work_blocks;
     return (blocks + 7) / 8 * 8;
 }
@@ -983,7 +982,9 @@ constexpr bool collaborative(int m) { return m == CTF_LIST || m == CTF_BOX || m 
 template <int METHOD, int P, template <int, int, bool, bool> class Go, class... Args>
 hipError_t dispatch_flags(const FilterArgs& a, Args&&... args)
 {
-    const bool st = a.tile_stats != nullptr;
+    // the instantiation with statistics also writes the texel lists; the
+    // plain one writes the per-pixel draws only
+    const bool st = a.tile_stats != nullptr || a.lists != nullptr;
     if constexpr (collaborative(METHOD)) {
         if (a.fallback != CTF_FB_STF1)
             return st ? Go<METHOD, P, true, true>::run(a, args...) : Go<METHOD, P, false, true>::run(a, args...);
@@ -998,14 +999,15 @@ struct GoFilter {
         static hipError_t run(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
         {
             const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
+            const int64_t least = counter_min_blocks(a.ntiles, kDecWaves);
             if constexpr (FILTER == CTF_FILTER_BILINEAR && !FB && METHOD != CTF_BILINEAR4) {
                 // (the 4-tap filter's full tiles of 256 rows never share a batch)
                 auto k = k_filter_dec_batch<METHOD, P, STATS>;
-                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work, least);
                 hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
             } else {
                 auto k = k_filter_dec<METHOD, P, STATS, FB, FILTER>;
-                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+                const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work, least);
                 hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, d);
             }
             return hipGetLastError();
@@ -1095,7 +1097,8 @@ struct GoLayers {
         {
             const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
             auto k = k_filter_layers<METHOD, P, STATS, FB, FILTER>;
-            const int64_t blocks = resident_blocks(k, 64 * kDecWaves, work);
+            const int64_t blocks =
+                resident_blocks(k, 64 * kDecWaves, work, counter_min_blocks(a.ntiles * LS.n, kDecWaves));
             hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
             return hipGetLastError();
         }

@@ -467,6 +467,8 @@ hipError_t launch_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
+    const int64_t least = counter_min_blocks(a.ntiles, kWavesPerBlock);   // 32-bit frame counters
+    if (blocks < least) blocks = least;
     const dim3 grid((unsigned)blocks);
     const dim3 block(kWave * kWavesPerBlock);
     if (a.tile_stats)

@@ -623,6 +623,8 @@ hipError_t launch_w32_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t 
     const int64_t npairs = (a.ntiles + 1) / 2;
     int64_t blocks = (npairs + kW32Waves - 1) / kW32Waves;
     if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
+    const int64_t least = counter_min_blocks(a.ntiles, kW32Waves);   // 32-bit frame counters
+    if (blocks < least) blocks = least;
     const dim3 grid((unsigned)blocks), block(kWave * kW32Waves);
     constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
     if (kCollab && a.fallback != CTF_FB_STF1) {
