@@ -497,22 +497,40 @@ __device__ inline bool stage_terms(const DevTexture& T, int4* terms_lds)
 
 // A texel from staged float terms (every lane reads the same entry, a
 // broadcast; the operands are then all vector registers, one instruction
-// fewer per term than with terms in scalar registers), else the texture's
-// own evaluation.  The same values either way.
+// fewer per term than with terms in scalar registers).  Textures whose
+// terms are not staged read them with vector loads: the scalar form would
+// hold 32 scalar registers for its eight terms in flight across the whole
+// kernel, and the per-lane kernels are short of scalar registers.  The same
+// values either way.
 template <int KIND>
 __device__ __forceinline__ float4 texel_eval_staged(const DevTexture& T, const int4* terms_lds, bool lds_float, int x,
                                                     int y)
 {
     if constexpr (KIND == CTF_TEX_SINUSOIDS) {
+        const int K = T.n_terms;
+        const int xm = x & (int)T.wmask, ym = y & (int)T.wmask;
+        const float xf = (float)xm, yf = (float)ym;
         if (lds_float) {
-            const int K = T.n_terms;
             const float4* tl = reinterpret_cast<const float4*>(terms_lds);
-            const float xf = (float)(x & (int)T.wmask), yf = (float)(y & (int)T.wmask);
             return make_float4(sinusoid_channel_f(tl + 0 * (K + 1), K, xf, yf),
                                sinusoid_channel_f(tl + 1 * (K + 1), K, xf, yf),
                                sinusoid_channel_f(tl + 2 * (K + 1), K, xf, yf),
                                sinusoid_channel_f(tl + 3 * (K + 1), K, xf, yf));
         }
+        // (an offset the compiler cannot prove uniform keeps these loads in
+        // vector registers)
+        int zero = 0;
+        asm volatile("" : "+v"(zero));
+        if (T.fterms) {
+            const float4* tf = T.fterms + zero;
+            return make_float4(sinusoid_channel_f(tf + 0 * K, K, xf, yf), sinusoid_channel_f(tf + 1 * K, K, xf, yf),
+                               sinusoid_channel_f(tf + 2 * K, K, xf, yf), sinusoid_channel_f(tf + 3 * K, K, xf, yf));
+        }
+        const int4* ti = T.terms + zero;
+        return make_float4(sinusoid_channel(ti + 0 * K, K, T.wmask, T.inv_w, xm, ym),
+                           sinusoid_channel(ti + 1 * K, K, T.wmask, T.inv_w, xm, ym),
+                           sinusoid_channel(ti + 2 * K, K, T.wmask, T.inv_w, xm, ym),
+                           sinusoid_channel(ti + 3 * K, K, T.wmask, T.inv_w, xm, ym));
     }
     return texel_eval<KIND>(T, x, y);
 }

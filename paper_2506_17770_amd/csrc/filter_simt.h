@@ -99,7 +99,10 @@ __device__ __forceinline__ int list_find(const WaveLds<F>& L, int n, uint64_t ke
     return lo;
 }
 
-template <int METHOD, int TEX, bool STATS, int FILTER>
+// FB: the instantiation that plans fallback C / C+ for failed waves (the
+// others fall back to one-tap STF only and carry none of that code, which
+// keeps their scalar registers for the common path).
+template <int METHOD, int TEX, bool STATS, int FILTER, bool FB>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterArgs a, DevTexture T)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
             pick = stf_pick_filter<FILTER>(f, h1, h2);
         }
         // fallback C / C+ for the lanes of A of a failed wave
-        const bool fallback = kCollab && !success && nA > 0 && a.fallback != CTF_FB_STF1;
+        const bool fallback = FB && kCollab && !success && nA > 0 && a.fallback != CTF_FB_STF1;
         FallbackPlan P{};
         if (fallback)
             P = plan_fallback<FILTER>(L, a.fallback, inA, nA, rankA, f, pick, pcg_hash(h2), fits16, xmin, ymin);
@@ -471,10 +474,18 @@ hipError_t launch_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
     if (blocks < least) blocks = least;
     const dim3 grid((unsigned)blocks);
     const dim3 block(kWave * kWavesPerBlock);
-    if (a.tile_stats)
-        hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER>), grid, block, 0, s, a, T);
-    else
-        hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER>), grid, block, 0, s, a, T);
+    constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    if (kCollab && a.fallback != CTF_FB_STF1) {
+        if (a.tile_stats)
+            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
+        else
+            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, kCollab>), grid, block, 0, s, a, T);
+    } else {
+        if (a.tile_stats)
+            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
+        else
+            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, false>), grid, block, 0, s, a, T);
+    }
     return hipGetLastError();
 }
 

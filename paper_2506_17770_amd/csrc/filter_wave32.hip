@@ -301,7 +301,8 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
     bool lds_float = false;
     if constexpr (kStage) lds_float = stage_terms(T, terms_lds) && T.fterms != nullptr;
     auto texel = [&](int x, int y) __attribute__((always_inline)) -> float4 {
-        return texel_eval_staged<TEX>(T, terms_lds, lds_float, x, y);
+        if constexpr (kStage) return texel_eval_staged<TEX>(T, terms_lds, lds_float, x, y);
+        else return texel_eval<TEX>(T, x, y);
     };
     FrameCounters fc;
     const int64_t npairs = (a.ntiles + 1) / 2;
