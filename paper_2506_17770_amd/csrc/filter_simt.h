@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
                 }
             };
             auto list_out = [&](int item, int2 e) {
-                if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = e;
+                if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = e;
             };
             // split-texel production: a successful wave with no one-tap
             // draws evaluates its 4n texel channels over all 64 lanes (lane l
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
         else evals = (success ? n : 0) + nstf;
 
         if (lane == 0) {
-            if (a.tile_stats) {
+            if (STATS && a.tile_stats) {
                 ctf_tile_stats S;
                 S.active = act;
                 S.part = A;
@@ -475,13 +475,15 @@ hipError_t launch_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
     const dim3 grid((unsigned)blocks);
     const dim3 block(kWave * kWavesPerBlock);
     constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    // the instantiation with statistics also writes the texel lists
+    const bool st = a.tile_stats != nullptr || a.lists != nullptr;
     if (kCollab && a.fallback != CTF_FB_STF1) {
-        if (a.tile_stats)
+        if (st)
             hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
         else
             hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, kCollab>), grid, block, 0, s, a, T);
     } else {
-        if (a.tile_stats)
+        if (st)
             hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
         else
             hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, false>), grid, block, 0, s, a, T);

@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                             ey = ymin + (t >> 4);
                         }
                     }
-                    if (a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = make_int2(ex, ey);
+                    if (STATS && a.lists) reinterpret_cast<int2*>(a.lists)[(size_t)tile * kMaxItems + item] = make_int2(ex, ey);
                 }
                 if (produce || draw_now) {
                     const float4 v = texel(ex, ey);
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(kWave * kW32Waves) void k_filter_w32(FilterArgs a, 
                 evals[hh] = (hh ? nprod1 : nprod0) + __popc(stfm[hh] & ~Am[hh]);
             else evals[hh] = (D[hh].success ? D[hh].n : 0) + __popc(stfm[hh]);
         }
-        if (ll == 0 && tile_ok && a.tile_stats) {
+        if (STATS && ll == 0 && tile_ok && a.tile_stats) {
             const HalfDecision& d = D[h];
             const uint64_t* Bh = h ? B1 : B0;
             ctf_tile_stats S;
@@ -628,11 +628,13 @@ hipError_t launch_w32_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t 
     if (blocks < least) blocks = least;
     const dim3 grid((unsigned)blocks), block(kWave * kW32Waves);
     constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
+    // the instantiation with statistics also writes the texel lists
+    const bool st = a.tile_stats != nullptr || a.lists != nullptr;
     if (kCollab && a.fallback != CTF_FB_STF1) {
-        if (a.tile_stats) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
+        if (st) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
         else hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER, kCollab>), grid, block, 0, s, a, T);
     } else {
-        if (a.tile_stats) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
+        if (st) hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
         else hipLaunchKernelGGL((k_filter_w32<METHOD, TEX, false, FILTER, false>), grid, block, 0, s, a, T);
     }
     return hipGetLastError();
