@@ -481,8 +481,10 @@ __device__ __forceinline__ float4 texel_eval(const DevTexture& T, int x, int y)
 // Terms of a sinusoid texture staged in a workgroup's LDS: [4][K + 1] entries
 // (each channel's row padded by one entry, so that lanes reading the same
 // term of different channels hit different banks), the float terms when the
-// texture has them.  Textures with more terms are not staged.
-constexpr int kLdsTerms = 64;
+// texture has them.  Textures with more terms are not staged.  62 terms:
+// 4032 bytes, so that a per-lane workgroup (four 7 KiB wave slices and the
+// terms) stays within 32 KiB and five of them fit in a CU's 160 KiB.
+constexpr int kLdsTerms = 62;
 constexpr int kLdsTermEntries = 4 * (kLdsTerms + 1);
 
 // Every thread of the workgroup calls this (it synchronises the workgroup).

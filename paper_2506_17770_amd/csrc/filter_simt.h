@@ -33,6 +33,8 @@ struct WaveLds {
     uint8_t rank[256];              // Mask: position t -> item index h^-1(t, B)
     uint8_t bytes[256];             // Mask: footprint-corner scatter before the ballots
 };
+static_assert(kWavesPerBlock * sizeof(WaveLds<2>) + kLdsTermEntries * sizeof(int4) <= 32768,
+              "a bilinear per-lane workgroup must fit five to a CU");
 
 // Exact set of the wave's texels as sorted unique keys (any box size): a
 // bitonic sort of the F^2 |A| footprint keys in LDS, then compaction of the
@@ -101,9 +103,19 @@ __device__ __forceinline__ int list_find(const WaveLds<F>& L, int n, uint64_t ke
 
 // FB: the instantiation that plans fallback C / C+ for failed waves (the
 // others fall back to one-tap STF only and carry none of that code, which
-// keeps their scalar registers for the common path).
+// keeps their scalar registers for the common path).  Bilinear: five waves
+// per SIMD (at most 96 vector registers; the workgroup's LDS fits five per
+// CU).  Bicubic: the LDS of the 16-tap footprints holds the occupancy lower,
+// the registers are left to the compiler.
+template <int FILTER>
+constexpr int simt_min_waves()
+{
+    return Taps<FILTER>::F == 2 ? 5 : 1;
+}
+
 template <int METHOD, int TEX, bool STATS, int FILTER, bool FB>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterArgs a, DevTexture T)
+__global__ __launch_bounds__(kWave * kWavesPerBlock, (simt_min_waves<FILTER>())) void k_filter_simt(FilterArgs a,
+                                                                                                  DevTexture T)
 {
     constexpr int F = Taps<FILTER>::F, O = Taps<FILTER>::O;
     constexpr bool kCanSplit = (METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK) &&
@@ -465,29 +477,26 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_filter_simt(FilterAr
 template <int METHOD, int TEX, int FILTER>
 hipError_t launch_m_t(const FilterArgs& a, const DevTexture& T, hipStream_t s)
 {
-    // grid-stride over tiles: up to 8 workgroups per CU, several tiles per wave
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
-    const int64_t least = counter_min_blocks(a.ntiles, kWavesPerBlock);   // 32-bit frame counters
-    if (blocks < least) blocks = least;
-    const dim3 grid((unsigned)blocks);
-    const dim3 block(kWave * kWavesPerBlock);
     constexpr bool kCollab = METHOD == CTF_LIST || METHOD == CTF_BOX || METHOD == CTF_MASK;
     // the instantiation with statistics also writes the texel lists
     const bool st = a.tile_stats != nullptr || a.lists != nullptr;
-    if (kCollab && a.fallback != CTF_FB_STF1) {
-        if (st)
-            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, kCollab>), grid, block, 0, s, a, T);
-        else
-            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, kCollab>), grid, block, 0, s, a, T);
-    } else {
-        if (st)
-            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, true, FILTER, false>), grid, block, 0, s, a, T);
-        else
-            hipLaunchKernelGGL((k_filter_simt<METHOD, TEX, false, FILTER, false>), grid, block, 0, s, a, T);
-    }
+    void (*k)(FilterArgs, DevTexture);
+    if (kCollab && a.fallback != CTF_FB_STF1)
+        k = st ? k_filter_simt<METHOD, TEX, true, FILTER, kCollab> : k_filter_simt<METHOD, TEX, false, FILTER, kCollab>;
+    else
+        k = st ? k_filter_simt<METHOD, TEX, true, FILTER, false> : k_filter_simt<METHOD, TEX, false, FILTER, false>;
+    // grid-stride over tiles: two rounds of the workgroups that fit on the
+    // chip at once (the second round evens out the tiles' uneven costs),
+    // several tiles per wave
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWave * kWavesPerBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 4;
+    int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > (int64_t)cus * per_cu * 2) blocks = (int64_t)cus * per_cu * 2;
+    const int64_t least = counter_min_blocks(a.ntiles, kWavesPerBlock);   // 32-bit frame counters
+    if (blocks < least) blocks = least;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0, s, a, T);
     return hipGetLastError();
 }
 

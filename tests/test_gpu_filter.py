@@ -116,6 +116,23 @@ def test_collaborative_equals_bilinear4_bitwise(G, c0, name, gk, ok, box, k):
     tex.close()
 
 
+@pytest.mark.parametrize("K", [62, 63, 64])
+@pytest.mark.parametrize("name,gk,ok,box,k", [METHODS[0], METHODS[2], METHODS[6]])
+def test_term_count_staging_boundary(G, c0, K, name, gk, ok, box, k):
+    """Up to 62 terms per channel the per-lane kernels read the texture's
+    terms from workgroup LDS, beyond that from memory: both forms give the
+    oracle's result."""
+    ctf, ctx, _ = G
+    sc = c0[0]
+    pqj, amp = cs.sinusoid_params(64, K, 8, seed=12)
+    tex = ctx.sinusoid_texture(64, pqj, amp)
+    otex = O.sinusoid_texture(64, pqj, amp)
+    g = run_gpu(G, sc.uv, sc.duv, tex, _method(G, gk, box, k), seed=5)
+    o = O.filter(sc.uv, sc.duv, otex, O.method(ok, box=box, k=k), seed=5, lists=True, stf=True)
+    compare(g, o, f"{name} K={K}")
+    tex.close()
+
+
 def test_texel_eval_matches_float64(G):
     ctf, ctx, torch = G
     W = 2048
