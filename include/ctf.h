@@ -91,7 +91,7 @@ enum { CTF_FILTER_BILINEAR = 0, CTF_FILTER_BSPLINE = 1, CTF_FILTER_CATMULL_ROM =
  * 4n channels of its n texels over all 64 lanes (item j / 4, channel j % 4
  * for j = lane, lane + 64, ...) whenever that takes fewer channel
  * evaluations per lane, ceil(n / 16), than one texel per lane of A,
- * 4 ceil(n / |A|); the terms are read from LDS (textures of at most 64 terms
+ * 4 ceil(n / |A|); the terms are read from LDS (textures of at most 62 terms
  * per channel).  Results are bit-identical either way. */
 enum { CTF_SPLIT_AUTO = 0, CTF_SPLIT_OFF = 1 };
 
