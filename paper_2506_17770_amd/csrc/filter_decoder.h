@@ -494,10 +494,77 @@ __device__ __forceinline__ bool lane_on_screen(const FilterArgs& a, int tx, int 
     return tx * kTile + (lane & 7) < a.sw && ty * kTile + (lane >> 3) < a.sh;
 }
 
+// XCD-aware share of the tiles for this wave.  Workgroups go round-robin
+// over the 8 XCDs, and XCD x takes the strips of kStripRows tile rows whose
+// index is x mod 8 (neighbouring tile rows, which share latent cells, stay
+// in one XCD's L2).  Contiguous eighths of the screen balance badly: the
+// texels a tile decodes vary down a frame (a minifying region decodes one
+// per pixel), so on the 4K benchmark frame the costliest eighth holds twice
+// the rows of the cheapest and its XCD finishes last.  The XCD's waves take
+// its tiles in turn (the launch makes the grid a multiple of 8).
+constexpr int kStripLog = 1;   // strips of 2 tile rows
+constexpr int kStripRows = 1 << kStripLog;
+
+struct Band {
+    int64_t end;   // every tile index is below it
+    int lw, nw, xcd;
+    __device__ Band(int64_t ntiles, int wid)
+    {
+        xcd = blockIdx.x & 7;
+        lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
+        nw = (int)(gridDim.x >> 3) * kDecWaves;
+        end = ntiles;
+    }
+};
+
+// A wave's walk over its XCD's tiles: the XCD's tile rows in order (row r of
+// the XCD is tile row ((r / kStripRows) * 8 + xcd) * kStripRows + r mod
+// kStripRows), each left to right, every nw-th tile from lw.  Past the last
+// one, tile reads INT64_MAX.
+struct StripWalk {
+    int64_t tile;
+    int tx, ty;
+    int row, xoff, dtx, drow, tiles_x, tiles_y;
+    __device__ __forceinline__ StripWalk(const Band& b, int64_t ntiles, int tiles_x_)
+    {
+        tiles_x = tiles_x_;
+        tiles_y = (int)(ntiles / tiles_x_);
+        xoff = b.xcd << kStripLog;
+        row = b.lw / tiles_x_;
+        tx = b.lw - row * tiles_x_;
+        drow = b.nw / tiles_x_;
+        dtx = b.nw - drow * tiles_x_;
+        place();
+    }
+    __device__ __forceinline__ void place()
+    {
+        ty = (((row >> kStripLog) << (3 + kStripLog)) + xoff) | (row & (kStripRows - 1));
+        tile = ty < tiles_y ? (int64_t)ty * tiles_x + tx : INT64_MAX;
+    }
+    __device__ __forceinline__ void advance()
+    {
+        tx += dtx;
+        row += drow;
+        if (tx >= tiles_x) {
+            tx -= tiles_x;
+            ++row;
+        }
+        place();
+    }
+};
+
+// Workgroups a launch needs so that no wave visits more than
+// kMaxWaveTileVisits tiles over its `layers` walks: an XCD's share of a
+// frame's tiles is at most an eighth plus one strip.
+inline int64_t dec_min_blocks(int64_t ntiles, int tiles_x, int layers)
+{
+    return counter_min_blocks((ntiles + (int64_t)8 * kStripRows * tiles_x) * layers, kDecWaves);
+}
+
 // Inputs of a tile for this lane, NaN (inactive) outside the band or screen
 // (per-lane 64-bit addresses: the per-tile kernels run faster with these
 // than with load_tile_px_s, measured).
-__device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
+__device__ __forceinline__ void load_tile_px(const FilterArgs& a, const StripWalk& t, int64_t band_e, float2& uv,
                                              float4& d)
 {
     const int lane = lane_id();
@@ -514,7 +581,7 @@ __device__ __forceinline__ void load_tile_px(const FilterArgs& a, const TileWalk
 
 // The same with a scalar tile base plus the lane's offset (the batched
 // kernel).
-__device__ __forceinline__ void load_tile_px_s(const FilterArgs& a, const TileWalk& t, int64_t band_e, float2& uv,
+__device__ __forceinline__ void load_tile_px_s(const FilterArgs& a, const StripWalk& t, int64_t band_e, float2& uv,
                                                float4& d)
 {
     uv = make_float2(__builtin_nanf(""), 0.f);
@@ -540,21 +607,6 @@ __device__ __forceinline__ void settle(const float2& uv, const float4& d)
 {
     asm volatile("" ::"v"(uv.x), "v"(uv.y), "v"(d.x), "v"(d.y), "v"(d.z), "v"(d.w));
 }
-
-// XCD-aware band of tiles for this wave: workgroups go round-robin over the
-// 8 XCDs, so band b of the screen is walked by the workgroups of XCD b.
-struct Band {
-    int64_t begin, end;
-    int lw, nw;
-    __device__ Band(int64_t ntiles, int wid)
-    {
-        const int xcd = blockIdx.x & 7;
-        lw = (int)(blockIdx.x >> 3) * kDecWaves + wid;
-        nw = (int)(gridDim.x >> 3) * kDecWaves;
-        begin = ntiles * xcd / 8;
-        end = ntiles * (xcd + 1) / 8;
-    }
-};
 
 // Waves per SIMD the register budget of the single-layer kernel is sized
 // for: the collaborative methods and the 4x4 full filter need the bound of
@@ -588,16 +640,16 @@ __global__ __launch_bounds__(64 * kDecWaves, (dec_waves_per_simd<METHOD, FILTER>
     // the inputs of the wave's next tile are loaded one tile ahead
     float2 uv_next;
     float4 d_next;
-    TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+    StripWalk next(band, a.ntiles, a.tiles_x);
     load_tile_px(a, next, band.end, uv_next, d_next);
     settle(uv_next, d_next);
     while (next.tile < band.end) {
-        const TileWalk cur = next;
+        const StripWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
         dec_tile<METHOD, P, STATS, FB, FILTER>(a, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc, [&] {
-            next.advance(band.nw);
+            next.advance();
             load_tile_px(a, next, band.end, uv_next, d_next);
         });
     }
@@ -894,7 +946,7 @@ __device__ __forceinline__ void batch_flush(const FilterArgs& a, BatchLds& BL, B
 template <int METHOD, int P, bool STATS>
 __device__ __forceinline__ void batch_add(const FilterArgs& a, BatchLds& BL, Batch& bt, const InferGrid& G,
                                           const FwdWeights<P>& W, const Biases& Bz, FrameCounters& fc,
-                                          const TileWalk& cur, const Footprint& f)
+                                          const StripWalk& cur, const Footprint& f)
 {
     const int lane = lane_id();
     const int R = plan_tile<METHOD, STATS>(a, BL, bt.npend, bt.rows, cur.tile, cur.tx, cur.ty, f, fc);
@@ -933,18 +985,18 @@ __global__ __launch_bounds__(64 * kDecWaves, 3) void k_filter_dec_batch(FilterAr
     Batch bt;
     float2 uv_next;
     float4 d_next;
-    TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+    StripWalk next(band, a.ntiles, a.tiles_x);
     load_tile_px_s(a, next, band.end, uv_next, d_next);
     settle(uv_next, d_next);
     while (next.tile < band.end) {
-        const TileWalk cur = next;
+        const StripWalk cur = next;
         const float2 uv = uv_next;
         const float4 d = d_next;
         // decode a full batch first, then request the next tile's inputs:
         // their latency is hidden by this tile's planning and the next
         // iteration's decode, and no wait inside the decode covers them
         if (bt.npend == 2) batch_flush<METHOD, P>(a, BL, bt, D.grid, W, Bz, fc);
-        next.advance(band.nw);
+        next.advance();
         load_tile_px_s(a, next, band.end, uv_next, d_next);
         const Footprint f = footprint(uv.x, uv.y, d, tex_w, tex_w);
         batch_add<METHOD, P, STATS>(a, BL, bt, D.grid, W, Bz, fc, cur, f);
@@ -999,7 +1051,7 @@ struct GoFilter {
         static hipError_t run(const FilterArgs& a, const DevDecoderWeights& d, hipStream_t s)
         {
             const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
-            const int64_t least = counter_min_blocks(a.ntiles, kDecWaves);
+            const int64_t least = dec_min_blocks(a.ntiles, a.tiles_x, 1);
             if constexpr (FILTER == CTF_FILTER_BILINEAR && !FB && METHOD != CTF_BILINEAR4) {
                 // (the 4-tap filter's full tiles of 256 rows never share a batch)
                 auto k = k_filter_dec_batch<METHOD, P, STATS>;
@@ -1067,11 +1119,11 @@ k_filter_layers(FilterArgs a, LayerSet LS)
         al.layer = (uint32_t)l;
         float2 uv_next;
         float4 d_next;
-        TileWalk next(band.begin + band.lw, band.nw, a.tiles_x);
+        StripWalk next(band, a.ntiles, a.tiles_x);
         load_tile_px(a, next, band.end, uv_next, d_next);
         settle(uv_next, d_next);
         while (next.tile < band.end) {
-            const TileWalk cur = next;
+            const StripWalk cur = next;
             const float2 uv = uv_next;
             const float4 d = d_next;
             // layer coordinates, float32: u' = fma(m01, v, m00 u), v' = fma(m11, v, m10 u)
@@ -1080,7 +1132,7 @@ k_filter_layers(FilterArgs a, LayerSet LS)
                                           __builtin_fmaf(m01, d.w, m00 * d.z), __builtin_fmaf(m11, d.w, m10 * d.z));
             const Footprint f = footprint(lu, lv, ld, tex_w, tex_w);
             dec_tile<METHOD, P, STATS, FB, FILTER>(al, D.grid, W, Bz, L, cur.tile, cur.tx, cur.ty, f, fc, [&] {
-                next.advance(band.nw);
+                next.advance();
                 load_tile_px(a, next, band.end, uv_next, d_next);
             });
         }
@@ -1098,7 +1150,7 @@ struct GoLayers {
             const int64_t work = (a.ntiles + kDecWaves - 1) / kDecWaves;
             auto k = k_filter_layers<METHOD, P, STATS, FB, FILTER>;
             const int64_t blocks =
-                resident_blocks(k, 64 * kDecWaves, work, counter_min_blocks(a.ntiles * LS.n, kDecWaves));
+                resident_blocks(k, 64 * kDecWaves, work, dec_min_blocks(a.ntiles, a.tiles_x, LS.n));
             hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kDecWaves), 0, s, a, LS);
             return hipGetLastError();
         }
