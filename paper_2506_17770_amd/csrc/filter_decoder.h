@@ -10,9 +10,10 @@
 // dense MLP pass over the wave's distinct texels.
 //
 // Waves are persistent: each loads the MLP weights into registers once and
-// walks a band of tiles.  Workgroups are dispatched round-robin over the 8
-// XCDs; band b of the screen goes to the workgroups of XCD b so that the
-// latent-grid reads of neighbouring tiles share an L2.
+// walks its share of the tiles.  Workgroups are dispatched round-robin over
+// the 8 XCDs; XCD x takes every eighth strip of two tile rows (Band), so
+// that the latent-grid reads of neighbouring tiles share an L2 while every
+// XCD gets a like share of the frame's work.
 //
 // Instantiated per reconstruction filter (FxF footprints, F = 2 or 4): the
 // bilinear kernels in filter_decoder.hip, the bicubic ones in
@@ -499,9 +500,10 @@ __device__ __forceinline__ bool lane_on_screen(const FilterArgs& a, int tx, int 
 // index is x mod 8 (neighbouring tile rows, which share latent cells, stay
 // in one XCD's L2).  Contiguous eighths of the screen balance badly: the
 // texels a tile decodes vary down a frame (a minifying region decodes one
-// per pixel), so on the 4K benchmark frame the costliest eighth holds twice
-// the rows of the cheapest and its XCD finishes last.  The XCD's waves take
-// its tiles in turn (the launch makes the grid a multiple of 8).
+// per pixel), so on a 3840x2160 frame of four planes the costliest eighth
+// decoded twice the rows of the cheapest and its XCD finished last.  The
+// XCD's waves take its tiles in turn (the launch makes the grid a multiple
+// of 8).
 constexpr int kStripLog = 1;   // strips of 2 tile rows
 constexpr int kStripRows = 1 << kStripLog;
 
